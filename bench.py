@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the super-point detection hot path on one MI355X.
+
+One step = one window of the 64 Mi-pair workload (1 router): the scan of every pair into the
+short estimator array vector and the long estimator array, then the end of window (candidate
+rebuild from the SEAV, LDCA filter against theta, report, reset).  Inputs are seeded synthetic
+traffic already resident in HBM when the timed region starts.
+
+Prints ONE JSON line: throughput in packets (pairs) per second for the library's default
+(binned) scan, the roofline of the dominant kernel (HIP events on the launch stream), p50/p99
+end-of-window latency, the same figures for the plain per-batch kernel (one thread per pair,
+global atomics), and the CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, public figure
+BYTES_PER_PAIR = 8             # algorithmic HBM bytes per pair: one uint32 (hip, oip) record
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "bin_kernel_plain_64m_traffic.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("spd_kernels.hip", "spd_internal.h"):
+        with open(os.path.join(ROOT, "paper_1901_07306_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
+    or None if the summary is missing or was taken on a different kernel source."""
+    try:
+        kv = {}
+        with open(PROFILE_TRAFFIC) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha") != kernel_source_sha():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def run_detector(spd, torch, params, x, steps, warmup, tune):
+    det = spd.Detector(params)
+    t = det.tuning
+    for k, v in tune.items():
+        setattr(t, k, v)
+    det.tuning = t
+    for _ in range(warmup):
+        det.scan(0, x)
+        det.close_window(0)
+    torch.cuda.synchronize()
+    det.profile_enable(True)
+    close_ms, window_ms = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec = None
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        det.scan(0, x)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        rec = det.close_window(0)
+        c1 = time.perf_counter()
+        close_ms.append((c1 - c0) * 1e3)
+        window_ms.append((c1 - s0) * 1e3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = det.profile()
+    stats = det.stats
+    det.close()
+    return elapsed, close_ms, window_ms, prof, rec, stats
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=5, help="steps for the plain per-batch kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path.  Several GPUs would each "
+              "scan their routers' pairs into their own sketches and OR-combine them once per window.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1901_07306_amd as spd
+    import synth_traffic as st
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    w = st.CONFIGS["plain_64m"]
+    log(f"generating {w.name}: {w.n_packets} pairs")
+    g0 = time.perf_counter()
+    win = st.gen_plain(w)
+    pairs = win.pairs[0]
+    log(f"generated in {time.perf_counter() - g0:.1f} s")
+    x = torch.from_numpy(pairs.view(np.int32)).to("cuda")
+    torch.cuda.synchronize()
+    n = x.shape[0]
+    params = spd.params_from(w.params)
+
+    # the library's default path (binned scan) -- the headline value
+    log(f"timing default scan: {args.warmup} warmup + {args.steps} steps")
+    el, close_ms, window_ms, prof, rec, stats = run_detector(spd, torch, params, x, args.steps, args.warmup, {})
+    value = n * args.steps / el
+    ms_step = el / args.steps * 1e3
+    kinds = {k: v for k, v in prof.items() if v[0]}
+    dom = max(kinds, key=lambda k: kinds[k][1])
+    dom_launches, dom_ms = kinds[dom]
+    avg_ms = dom_ms / dom_launches
+    alg_bytes = {"bin": BYTES_PER_PAIR * n, "direct": BYTES_PER_PAIR * n}.get(dom)
+    if alg_bytes is None:
+        raise RuntimeError(f"unexpected dominant kernel {dom}")
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    scan_kinds = ("bin", "transpose", "apply", "fill", "direct")
+    scan_ms = sum(kinds.get(k, (0, 0.0))[1] for k in scan_kinds) / args.steps
+    close_dev_ms = kinds.get("close", (0, 0.0))[1] / max(1, kinds.get("close", (1, 0))[0])
+    traffic = measured_traffic()
+
+    # the plain per-batch kernel: one thread per pair, global atomicOr into the sketches
+    log(f"timing plain scan: 1 warmup + {args.plain_steps} steps")
+    pel, pclose, pwin, pprof, prec, _ = run_detector(spd, torch, params, x, args.plain_steps, 1,
+                                                      {"direct_max_pairs": 1 << 62})
+    plain_value = n * args.plain_steps / pel
+    assert np.array_equal(prec, rec), "plain and binned scans disagree"
+
+    out = {
+        "metric": "packets/s scanned (1 GPU, % HBM roofline); p99 window-close latency, batched vs plain",
+        "value": value,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded; CAIDA-shaped core-network window)",
+        "config": {
+            "workload": "plain_64m: 1 router, 1 window of 64Mi (src,dst) uint32 pairs; 2M Zipf(1.1)<=500 "
+                        "sources, 500 planted super points |OP| in [1024,20000], 30% duplicates, theta 1024",
+            "method": {"r": w.params.r, "sr": w.params.sr, "a": w.params.a, "log2k": w.params.log2k,
+                       "lr": w.params.lr, "log2lc": w.params.log2lc, "theta": w.params.theta},
+            "step": "scan 64Mi pairs (binned LDS scan) + end of window (rebuild, filter, report, reset)",
+            "parallelism": "1 GPU",
+        },
+        "roofline": {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": avg_ms,
+            "launches": dom_launches,
+        },
+        "scan_ms_per_window": scan_ms,
+        "scan_roofline_frac": (BYTES_PER_PAIR * n / (scan_ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
+        "close_device_ms": close_dev_ms,
+        "close_latency_ms": {"p50": pct(close_ms, 50), "p99": pct(close_ms, 99)},
+        "window_latency_ms": {"p50": pct(window_ms, 50), "p99": pct(window_ms, 99)},
+        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in kinds.items()},
+        "reported_super_points": int(len(rec)),
+        "plain": {
+            "value": plain_value,
+            "unit": "packets/s",
+            "ms_per_step": pel / args.plain_steps * 1e3,
+            "close_latency_ms": {"p50": pct(pclose, 50), "p99": pct(pclose, 99)},
+            "window_latency_ms": {"p50": pct(pwin, 50), "p99": pct(pwin, 99)},
+            "kernel": "direct (one thread per pair, global atomicOr)",
+        },
+        "batched_over_plain": value / plain_value,
+        "gpu": torch.cuda.get_device_name(0),
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the CPU oracle on the host (one full window, single thread)")
+        c0 = time.perf_counter()
+        sk = oracle.Sketch(oracle.params(w.params)).scan(pairs)
+        ref = sk.detect()
+        cel = time.perf_counter() - c0
+        out["cpu_baseline"] = {"value": n / cel, "unit": "packets/s", "cores": 1, "kind": "oracle",
+                               "sample": "the full 64Mi-pair window once: scan + end of window, single thread",
+                               "seconds": cel}
+        out["oracle_match"] = bool(np.array_equal(ref.astype(rec.dtype), rec))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

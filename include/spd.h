@@ -1,0 +1,206 @@
+/*
+ * libspd: super-point detection on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the detection scheme of Xu, Ding and Hu, "Most memory efficient distributed super
+ * points detection on core networks" (arXiv 1901.07306): every (hip, oip) IPv4 pair of a time
+ * window is recorded in a short estimator array vector (SEAV, Section 3.2) and a linear distinct
+ * counter array (LDCA, Section 3.3); each router (watch point) keeps its own pair of sketches,
+ * the sketches are merged by OR (Section 4.2), and at the end of a window super-point candidates
+ * are rebuilt from the SEAV and filtered by their LDCA estimate against the threshold theta
+ * (Definition 2).  A sliding-window mode replaces every bit by a time stamp (Section 5).
+ *
+ * Conventions for every entry point:
+ *  - Status codes: SPD_OK (0) or a negative SPD_E_* value; nothing is thrown across the ABI.
+ *    spd_last_error() returns a message for the last failure on a context.
+ *  - Pair buffers are DEVICE pointers owned by the caller: n_pairs records of two uint32
+ *    (element 0 = hip, the monitored host; element 1 = oip, its opposite IP), 8-byte aligned.
+ *    They must stay valid until the stream has passed the scan.
+ *  - Streams are hipStream_t values passed as void* (NULL = the null stream).  Scans, merges
+ *    and slides are asynchronous on that stream; close, export and import synchronise it.
+ *  - The library owns all sketch state, in device memory of the device that was current at
+ *    spd_create().  A context is not thread-safe: one host thread drives it, or callers lock.
+ *  - Canonical layouts (export/import, also the device layouts):
+ *      SEAV: uint8  [2^r][SR rows][2^IBN(row)]   (rows of one SEA stored one after another)
+ *      LDCA: uint32 [LR][LC][k/32]               (bit q of LDC (i, c) = bit q%32 of word q/32)
+ */
+#ifndef SPD_H
+#define SPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t spd_status;
+
+#define SPD_OK 0
+#define SPD_E_INVALID (-1)    /* bad argument, parameter out of range or layout constraint broken */
+#define SPD_E_NOMEM (-2)      /* the HBM budget given to spd_create() would be exceeded */
+#define SPD_E_HIP (-3)        /* HIP runtime error; spd_last_error() has its text */
+#define SPD_E_TRUNCATED (-4)  /* output capacity too small; *n_out holds the required count */
+#define SPD_E_STATE (-5)      /* call not valid in the context's current state (e.g. bad router) */
+
+#define SPD_MAX_ROWS 8        /* largest SR and LR */
+#define SPD_GLOBAL (-1)       /* target id of the merged (global) sketch */
+
+/* Method parameters.  Sections cited per field. */
+typedef struct spd_params {
+    uint32_t theta;            /* super-point threshold, Definition 2; 1 <= theta <= 2^31 */
+    uint32_t r;                /* right-part bits: the SEAV holds 2^r SEAs (Section 3.2); r <= 24 */
+    uint32_t sr;               /* rows per SEA, 1..SPD_MAX_ROWS */
+    uint32_t a;                /* extra index bits per row (Section 3.2 example: IBN = ceil(L/SR) + a) */
+    uint32_t explicit_layout;  /* 0: derive isb/ibn from (r, sr, a); 1: use isb/ibn as given */
+    uint32_t isb[SPD_MAX_ROWS];/* index starting bit of each row, Definition 3 */
+    uint32_t ibn[SPD_MAX_ROWS];/* index bit count of each row, Definition 4; 2..16 */
+    uint32_t log2k;            /* LDC length k = 2^log2k bits (Section 3.3); 5..16 */
+    uint32_t lr;               /* LDCA rows, 1..SPD_MAX_ROWS */
+    uint32_t log2lc;           /* LDCA columns LC = 2^log2lc; 0..24 */
+    uint32_t window_slices;    /* 0: discrete window; K > 0: sliding window of K slices (Section 5) */
+    /* Multiply-add-shift hashes h(x) = ((mul * x + add) mod 2^64) >> (64 - bits), mul odd:
+     * index 0 = H1 (32 bits), 1 = H2 (3 bits), 2 = H3 (log2k bits), 3 + i = LH_i (log2lc bits). */
+    uint64_t hash_mul[3 + SPD_MAX_ROWS];
+    uint64_t hash_add[3 + SPD_MAX_ROWS];
+} spd_params;
+
+/* Host-side constants derived from spd_params (Eq. 1, Definitions 3-4, Eq. 4). */
+typedef struct spd_derived {
+    uint32_t tau;              /* Eq. 1: smallest t >= 0 with 8 * 2^t >= theta */
+    uint32_t z_theta;          /* Eq. 4: largest z0 in [1, k] with -k ln(z0/k) >= theta (0: none) */
+    uint32_t isb[SPD_MAX_ROWS];
+    uint32_t ibn[SPD_MAX_ROWS];
+    uint64_t sea_bytes;        /* bytes of one SEA */
+    uint64_t seav_bytes;       /* 2^r * sea_bytes */
+    uint64_t ldca_words;       /* LR * LC * k / 32 */
+} spd_derived;
+
+/* One super point reported at the end of a window. */
+typedef struct spd_superpoint {
+    uint32_t ip;               /* the host */
+    uint32_t z0;               /* zero bits of its ULDC (AND of its LR LDCs) */
+    uint32_t est;              /* Eq. 4 estimate -k ln(z0/k) rounded to nearest (z0 = 0 read as 1) */
+    uint32_t flags;            /* bit 0: saturated (z0 == 0) */
+} spd_superpoint;
+
+/* One batch of a fused multi-router scan. */
+typedef struct spd_batch {
+    uint32_t router;           /* router (watch point) id, 0..n_routers-1 */
+    uint32_t reserved;         /* must be 0 */
+    const uint32_t *pairs_dev; /* device pointer to n_pairs (hip, oip) records */
+    uint64_t n_pairs;
+} spd_batch;
+
+/* Launch tuning.  Every setting gives the same sketch bits; only speed changes. */
+typedef struct spd_tuning {
+    uint64_t direct_max_pairs; /* batches up to this size use the direct-atomic scan kernel */
+    uint32_t bucket_bits;      /* binned scan: log2 of sketch bits per LDS bucket (12..20) */
+    uint32_t tile_pairs;       /* binned scan: pairs per tile (power of two, 2048..16384) */
+    uint32_t bin_block;        /* binned scan: threads per workgroup of the binning kernel (256..1024) */
+    uint32_t apply_block;      /* binned scan: threads per workgroup of the apply kernel (256..1024) */
+    uint32_t direct_block;     /* direct scan: threads per workgroup */
+    uint32_t direct_grid_per_cu; /* direct scan: workgroups per compute unit */
+    uint32_t seav_lds;         /* direct scan: 1 = keep a per-workgroup LDS copy of the SEAV when it fits */
+    uint32_t close_block;      /* end-of-window kernel: threads per workgroup */
+} spd_tuning;
+
+typedef struct spd_stats {
+    uint64_t pairs_scanned;
+    uint64_t direct_launches;
+    uint64_t binned_launches;
+    uint64_t closes;
+    uint64_t candidates_last;  /* candidates rebuilt at the last close (before the LDCA filter) */
+    uint64_t reported_last;
+    uint64_t device_bytes;     /* device memory held by the context */
+} spd_stats;
+
+/* Kernel kinds timed by the optional profiler. */
+#define SPD_K_DIRECT 0     /* direct-atomic scan */
+#define SPD_K_STAMP 1      /* sliding-window scan */
+#define SPD_K_BIN 2        /* binned scan, phase 1: tile binning */
+#define SPD_K_TRANSPOSE 3  /* binned scan: per-tile offsets transposed to per-bucket rows */
+#define SPD_K_APPLY 4      /* binned scan, phase 2: bucket apply */
+#define SPD_K_MERGE 5      /* router merge */
+#define SPD_K_CLOSE 6      /* end-of-window candidate rebuild and filter */
+#define SPD_K_FILL 7       /* clears (window reset, counters) */
+#define SPD_K_KINDS 8
+
+typedef struct spd_profile {
+    uint64_t launches[SPD_K_KINDS];
+    double total_ms[SPD_K_KINDS];  /* summed device time between HIP events around each launch */
+} spd_profile;
+
+typedef struct spd_ctx spd_ctx;
+
+/* Derive the host constants of p without touching the GPU (Eq. 1, Section 3.2 layout and its
+ * two constraints, Eq. 4).  SPD_E_INVALID if p is out of range or the layout breaks a constraint. */
+spd_status spd_derive(const spd_params *p, spd_derived *out);
+
+/* Create a context for n_routers routers (watch points, Section 4) plus one global sketch, all
+ * zero, on the current HIP device.  hbm_budget_bytes bounds the device memory the context may
+ * hold (0 = no bound); SPD_E_NOMEM if the sketches alone exceed it.  *out receives the context. */
+spd_status spd_create(const spd_params *p, uint32_t n_routers, uint64_t hbm_budget_bytes, spd_ctx **out);
+
+/* Release every device and host resource of ctx (synchronises the device). */
+void spd_destroy(spd_ctx *ctx);
+
+/* Record n_pairs pairs seen at one router into its sketches (Sections 3.1-3.3, Section 4.1).
+ * The scan is order-free and idempotent: the sketch depends only on the set of distinct pairs.
+ * Sliding mode: the pairs belong to the current slice.  n_pairs = 0 is a no-op. */
+spd_status spd_scan(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_dev, uint64_t n_pairs, void *stream);
+
+/* Record several batches, from any routers and of any sizes, in one fused pass (same result as
+ * calling spd_scan on each batch). */
+spd_status spd_scan_batches(spd_ctx *ctx, const spd_batch *batches, uint32_t n_batches, void *stream);
+
+/* Merge (Section 4.2): global sketch = bitwise OR of the listed routers' sketches (sliding mode:
+ * element-wise maximum of time stamps, whose bit view is the OR).  The previous global content
+ * is replaced.  Order-free; listing a router twice changes nothing. */
+spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *stream);
+
+/* End of window for a target (router id or SPD_GLOBAL): rebuild the candidates from the SEAV
+ * (Section 3.2, Eq. 3), keep those whose ULDC estimate reaches theta (Section 3.3, Eq. 4), and
+ * write them to out_host (host memory) sorted by ip ascending.  *n_out = number of super points;
+ * if it exceeds cap the first cap are written and SPD_E_TRUNCATED is returned.
+ * Discrete mode: the target's sketch is then reset to zero (a new window starts).
+ * Sliding mode: reports the window of the last K slices; nothing is reset. */
+spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_host, uint32_t cap,
+                            uint32_t *n_out, void *stream);
+
+/* Sliding mode only: the next scans belong to the next time slice (Section 5.2).  Stamps older
+ * than the window simply drop out of the bit view; no state is rewritten. */
+spd_status spd_slide(spd_ctx *ctx, void *stream);
+
+/* Copy a target's sketch to host memory in the canonical layouts (seav_host: seav_bytes bytes,
+ * ldca_host: ldca_words words).  Sliding mode: the bit view of the current window. */
+spd_status spd_export(spd_ctx *ctx, int32_t target, uint8_t *seav_host, uint32_t *ldca_host);
+
+/* Replace a target's sketch by host data in the canonical layouts (discrete mode only). */
+spd_status spd_import(spd_ctx *ctx, int32_t target, const uint8_t *seav_host, const uint32_t *ldca_host);
+
+/* Sliding mode: copy a target's raw time stamps (1 + last slice that set the bit, 0 = never):
+ * seav_ts_host holds seav_bytes * 8 entries (bit b of byte x at 8x + b), ldca_ts_host holds
+ * ldca_words * 32 entries (one per LDCA bit). */
+spd_status spd_export_stamps(spd_ctx *ctx, int32_t target, uint16_t *seav_ts_host, uint16_t *ldca_ts_host);
+
+/* Current slice index (sliding mode; 0 in discrete mode). */
+uint32_t spd_current_slice(const spd_ctx *ctx);
+
+/* Turn per-kernel timing on (1) or off (0) and reset its totals.  When on, every kernel launch
+ * is bracketed by two HIP events recorded on the launch stream. */
+spd_status spd_profile_enable(spd_ctx *ctx, uint32_t on);
+
+/* Totals since the last spd_profile_enable(); waits for the recorded events. */
+spd_status spd_get_profile(spd_ctx *ctx, spd_profile *out);
+
+spd_status spd_get_tuning(const spd_ctx *ctx, spd_tuning *out);
+spd_status spd_set_tuning(spd_ctx *ctx, const spd_tuning *t);
+spd_status spd_get_stats(const spd_ctx *ctx, spd_stats *out);
+
+const char *spd_strerror(spd_status s);
+const char *spd_last_error(const spd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPD_H */

@@ -1,0 +1,111 @@
+"""Autotuner for the scan launch settings of libspd.
+
+Every setting gives identical sketch bits; only speed changes.  The tuner times the scan of a
+representative device batch under each candidate setting (device time from the library's own
+HIP-event profiler) and keeps the fastest.  It also finds the batch size above which the binned
+scan beats the direct-atomic kernel, which decides the path per batch and the batch grouping of
+the serving loop.  Results are cached in memory per (GPU name, method parameters, batch size).
+"""
+from __future__ import annotations
+
+import itertools
+from typing import Dict, List, Optional, Tuple
+
+_CACHE: Dict[tuple, dict] = {}
+
+SCAN_KINDS = ("direct", "bin", "transpose", "apply", "fill")
+
+
+def _scan_ms(det, x, reps: int) -> float:
+    det.profile_enable(True)
+    for _ in range(reps):
+        det.scan(0, x)
+    prof = det.profile()
+    det.profile_enable(False)
+    det.close_window(0)
+    return sum(prof[k][1] for k in SCAN_KINDS) / reps
+
+
+def candidate_settings(quick: bool = False) -> List[dict]:
+    if quick:
+        return [dict(bucket_bits=20, tile_pairs=16384, bin_block=1024, apply_block=1024),
+                dict(bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024),
+                dict(bucket_bits=19, tile_pairs=8192, bin_block=512, apply_block=512)]
+    out = []
+    for S, T, bb, ab in itertools.product((19, 20), (8192, 16384), (512, 1024), (512, 1024)):
+        out.append(dict(bucket_bits=S, tile_pairs=T, bin_block=bb, apply_block=ab))
+    return out
+
+
+def tune_binned(det, x, reps: int = 3, quick: bool = False) -> Tuple[dict, List[Tuple[dict, float]]]:
+    """Fastest binned-scan setting for batch x on detector det (router 0 is used and reset)."""
+    base = det.tuning
+    table = []
+    for cand in candidate_settings(quick):
+        t = det.tuning
+        for k, v in cand.items():
+            setattr(t, k, v)
+        t.direct_max_pairs = 0
+        try:
+            det.tuning = t
+        except Exception:
+            continue
+        _scan_ms(det, x, 1)   # warm-up (scratch growth)
+        table.append((cand, _scan_ms(det, x, reps)))
+    det.tuning = base
+    best = min(table, key=lambda e: e[1])[0]
+    return best, table
+
+
+def tune_direct(det, x, reps: int = 3) -> Tuple[dict, List[Tuple[dict, float]]]:
+    base = det.tuning
+    table = []
+    for block, per_cu, lds in itertools.product((256, 512), (4, 8, 16), (0, 1)):
+        t = det.tuning
+        t.direct_max_pairs = 1 << 62
+        t.direct_block, t.direct_grid_per_cu, t.seav_lds = block, per_cu, lds
+        det.tuning = t
+        _scan_ms(det, x, 1)
+        table.append((dict(direct_block=block, direct_grid_per_cu=per_cu, seav_lds=lds), _scan_ms(det, x, reps)))
+    det.tuning = base
+    return min(table, key=lambda e: e[1])[0], table
+
+
+def crossover(det, x, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22), reps: int = 5) -> int:
+    """Largest tested batch size at which the direct kernel is still at least as fast."""
+    base = det.tuning
+    best = 0
+    for n in sizes:
+        if n > x.shape[0]:
+            break
+        xs = x[:n]
+        t = det.tuning
+        t.direct_max_pairs = 1 << 62
+        det.tuning = t
+        _scan_ms(det, xs, 1)
+        d = _scan_ms(det, xs, reps)
+        t.direct_max_pairs = 0
+        det.tuning = t
+        _scan_ms(det, xs, 1)
+        b = _scan_ms(det, xs, reps)
+        if d <= b:
+            best = n
+    det.tuning = base
+    return best
+
+
+def autotune(det, x, key: Optional[tuple] = None, quick: bool = False) -> dict:
+    """Tune det for batches like x and apply the result.  Returns the chosen settings."""
+    import torch
+    key = key or (torch.cuda.get_device_name(0), tuple(det.params.hash_mul[:3]), det.params.r,
+                  det.params.log2lc, int(x.shape[0]))
+    if key not in _CACHE:
+        b, _ = tune_binned(det, x, quick=quick)
+        d, _ = tune_direct(det, x[: min(x.shape[0], 1 << 20)])
+        cross = crossover(det, x)
+        _CACHE[key] = dict(b, **d, direct_max_pairs=cross)
+    t = det.tuning
+    for k, v in _CACHE[key].items():
+        setattr(t, k, v)
+    det.tuning = t
+    return dict(_CACHE[key])

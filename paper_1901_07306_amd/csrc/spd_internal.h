@@ -1,0 +1,133 @@
+// Internal declarations shared by the kernels and the host runtime of libspd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spd.h"
+
+namespace spd {
+
+constexpr int kMaxRows = SPD_MAX_ROWS;
+constexpr uint32_t kSeHot = 3;      // an SE of weight >= 3 is judged to have >= theta peers (Section 3.1)
+constexpr int kMaxGroup = 32;       // batches / slots per fused launch (kernel-argument arrays)
+
+// Method constants of one context, passed by value to every kernel.
+struct Consts {
+    uint64_t mul[3 + kMaxRows];     // hash multipliers: H1, H2, H3, LH_0..
+    uint64_t add[3 + kMaxRows];     // hash addends
+    uint32_t tau_mask;              // (1 << tau) - 1: sampled iff (H1(oip) & tau_mask) == 0
+    uint32_t r, L, sr, lr;          // L = 32 - r bits of LP
+    uint32_t rmask;                 // 2^r - 1
+    uint32_t log2k, log2lc;
+    uint32_t isb[kMaxRows];
+    uint32_t ibn[kMaxRows];
+    uint32_t row_off[kMaxRows];     // byte offset of each row inside one SEA
+    uint32_t sea_bytes;
+    uint32_t z_theta;
+    uint64_t ldca_bits;             // LR * LC * k
+    uint64_t seav_bytes;            // canonical SEAV bytes (the allocation may be padded)
+};
+
+// ------------------------------------------------------------------------------ device math
+// High 32 bits of (mul * x + add) mod 2^64: the multiply-add-shift hash before its final shift.
+__device__ __forceinline__ uint32_t mas_hi(uint32_t x, uint64_t mul, uint64_t add) {
+    uint64_t lo = (uint64_t)(uint32_t)mul * x + add;
+    return (uint32_t)(lo >> 32) + (uint32_t)(mul >> 32) * x;
+}
+
+__device__ __forceinline__ uint32_t top_bits(uint32_t h, uint32_t m) { return m ? h >> (32u - m) : 0u; }
+
+// Eq. 2: Idx(i, LP) = IBN(i) consecutive bits of LP starting at ISB(i), wrapping modulo L.
+// Rotating a doubled copy of LP gives the wrapped window in one shift.
+__device__ __forceinline__ uint32_t row_index(uint32_t lp, uint32_t isb, uint32_t ibn, uint32_t L) {
+    uint64_t d = (uint64_t)lp | ((uint64_t)lp << L);
+    return (uint32_t)(d >> isb) & ((1u << ibn) - 1u);
+}
+
+// Inverse placement used by Eq. 3: the LP bits that a row index c of row (isb, ibn) stands for.
+__device__ __forceinline__ uint32_t row_bits_in_lp(uint32_t c, uint32_t isb, uint32_t L) {
+    uint64_t t = (uint64_t)c << isb;
+    uint64_t lmask = (L == 32) ? 0xFFFFFFFFull : ((1ull << L) - 1ull);
+    return (uint32_t)((t | (t >> L)) & lmask);
+}
+
+// LDCA bit address of (row i, column c, bit q): ((i * LC + c) * k) + q.
+__device__ __forceinline__ uint32_t ldca_bit(uint32_t i, uint32_t col, uint32_t q, const Consts &k) {
+    return (((i << k.log2lc) | col) << k.log2k) | q;
+}
+
+// SEAV byte offset of row i's cell for host hip (RP selects the SEA, LP the cell, Eq. 2).
+__device__ __forceinline__ uint32_t seav_byte(uint32_t hip, uint32_t i, const Consts &k) {
+    uint32_t rp = hip & k.rmask;
+    uint32_t lp = (uint32_t)((uint64_t)hip >> k.r);
+    return rp * k.sea_bytes + k.row_off[i] + row_index(lp, k.isb[i], k.ibn[i], k.L);
+}
+
+// ------------------------------------------------------------------------------ launchers
+struct SlotPtrs {
+    uint8_t *seav;       // padded SEAV (word aligned)
+    uint32_t *ldca;
+    uint16_t *seav_ts;   // sliding mode
+    uint16_t *ldca_ts;
+};
+
+struct BatchDesc {
+    const uint32_t *pairs;
+    uint64_t n;
+    uint32_t first_tile;
+    uint32_t slot;       // index into the launch's slot table
+};
+
+struct BinGeometry {
+    uint32_t S;          // log2 of bits per bucket
+    uint32_t nb_ldca;    // buckets covering the LDCA
+    uint32_t nb;         // total buckets (LDCA then padded SEAV)
+    uint32_t tile_pairs;
+    uint32_t scap;       // sampled pairs staged in LDS per tile
+    uint32_t cap;        // items reserved per tile (multiple of 6)
+    uint32_t region;     // 32-bit words per tile in the item buffer: items packed 3 per 64 bits
+    uint32_t block;      // threads per binning workgroup
+    uint32_t lds_bytes;  // dynamic LDS of the binning kernel
+};
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n_words, uint32_t value, hipStream_t s);
+hipError_t launch_scan_direct(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
+                              uint32_t block, uint32_t grid, bool seav_lds, hipStream_t s);
+hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
+                             uint16_t stamp, uint32_t block, uint32_t grid, hipStream_t s);
+hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+                      uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s);
+hipError_t launch_transpose(const uint32_t *meta, uint32_t *metaT, uint32_t rows, uint32_t cols, hipStream_t s);
+struct ApplySlot {
+    uint32_t *ldca;
+    uint32_t *seav_w;
+    uint32_t tile_lo, tile_hi;
+    uint32_t fresh;
+    uint32_t pad;
+};
+hipError_t launch_apply(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
+                        const uint32_t *metaT, uint32_t n_tiles, uint32_t block, hipStream_t s);
+hipError_t launch_or_merge(uint32_t *dst, const uint32_t *const *src, uint32_t n_src, uint64_t n_words, hipStream_t s);
+hipError_t launch_max_merge_u16(uint16_t *dst, const uint16_t *const *src, uint32_t n_src, uint64_t n_elems,
+                                hipStream_t s);
+hipError_t launch_renormalize_u16(uint16_t *p, uint64_t n, uint16_t off, hipStream_t s);
+hipError_t launch_bit_view(const uint16_t *ts, uint64_t n_bits, uint16_t thr, uint32_t *out_words, hipStream_t s);
+
+struct CloseArgs {
+    const uint8_t *seav;
+    const uint32_t *ldca;
+    const uint16_t *seav_ts;
+    const uint16_t *ldca_ts;
+    uint32_t thr;        // sliding: stamp threshold of the bit view
+    uint32_t *rec;       // (ip, z0) pairs
+    uint32_t *counters;  // [0] reported, [1] candidates
+    uint32_t rec_cap;
+    uint32_t n_rp;
+    uint32_t list_stride;
+    uint32_t qcap;
+};
+hipError_t launch_close(const Consts &c, const CloseArgs &a, bool sliding, uint32_t block, uint32_t grid,
+                        hipStream_t s);
+
+}  // namespace spd

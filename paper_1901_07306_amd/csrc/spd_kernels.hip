@@ -1,0 +1,735 @@
+// HIP kernels of libspd for gfx950 (MI355X).
+//
+// Scan (Sections 3.1-3.3, 4.1): every pair sets LR bits of the LDCA and, when sampled, SR bits of
+// the SEAV.  Two kernels record a batch:
+//   * direct:  one thread per pair, global atomicOr per bit.  Device-wide random atomics run at a
+//              fixed rate on MI355X whatever the footprint, so this path serves small batches.
+//   * binned:  k_bin reads a tile of pairs, turns each pair into bit addresses, counting-sorts them
+//              in LDS by sketch bucket (2^S bits) and writes the tile's items bucket-major with
+//              coalesced stores; k_apply gives one workgroup per bucket, replays every tile's
+//              segment for that bucket into an LDS bitmap with LDS atomicOr, and writes the
+//              bucket back with plain stores.  No global atomics on the hot path.
+// End of window (Sections 3.2-3.3): k_close gives one wavefront per SEA (one RP): hot-SE lists
+// by ballot, the candidate product with Eq. 3 consistency and the SEU weight test, then the
+// ULDC of each candidate (AND over LR rows, popcount by wavefront reduction).
+#include "spd_internal.h"
+
+namespace spd {
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct BatchTable {
+    BatchDesc b[kMaxGroup];
+    uint32_t n;
+};
+struct SlotTable {
+    SlotPtrs s[kMaxGroup];
+};
+struct ApplyTable {
+    ApplySlot s[kMaxGroup];
+};
+struct SrcTable {
+    const uint32_t *p[kMaxGroup];
+};
+struct SrcTable16 {
+    const uint16_t *p[kMaxGroup];
+};
+
+__device__ __forceinline__ void global_or(uint32_t *p, uint32_t v) {
+    __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool sampled(uint32_t oip, const Consts &c) {
+    // lsb(H1(oip)) >= tau, with lsb(0) = 32 (Section 3.1): the low tau bits are all zero.
+    return (mas_hi(oip, c.mul[0], c.add[0]) & c.tau_mask) == 0u;
+}
+
+__device__ __forceinline__ uint32_t se_bit(uint32_t oip, const Consts &c) { return mas_hi(oip, c.mul[1], c.add[1]) >> 29; }
+
+__device__ __forceinline__ uint32_t ldc_bit(uint32_t oip, const Consts &c) {
+    return top_bits(mas_hi(oip, c.mul[2], c.add[2]), c.log2k);
+}
+
+__device__ __forceinline__ uint32_t ldc_col(uint32_t hip, uint32_t i, const Consts &c) {
+    return top_bits(mas_hi(hip, c.mul[3 + i], c.add[3 + i]), c.log2lc);
+}
+
+// ------------------------------------------------------------------------------ fill
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
+    uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t n4 = n / 4;
+    u32x4 vv = {v, v, v, v};
+    for (uint64_t j = i; j < n4; j += stride) reinterpret_cast<u32x4 *>(p)[j] = vv;
+    for (uint64_t j = n4 * 4 + i; j < n; j += stride) p[j] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n_words, uint32_t value, hipStream_t s) {
+    if (n_words == 0) return hipSuccess;
+    uint64_t blocks = (n_words / 4 + 255) / 256;
+    uint32_t grid = (uint32_t)(blocks < 4096 ? (blocks ? blocks : 1) : 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, s, p, n_words, value);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------ direct scan
+template <bool SEAV_LDS>
+__global__ __launch_bounds__(1024) void k_scan_direct(Consts c, BatchTable bt, SlotTable st, uint32_t lds_words) {
+    extern __shared__ uint32_t lds[];
+    if (SEAV_LDS) {
+        for (uint32_t w = threadIdx.x; w < lds_words; w += blockDim.x) lds[w] = 0;
+        __syncthreads();
+    }
+    const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint32_t bi = 0; bi < bt.n; ++bi) {
+        const BatchDesc B = bt.b[bi];
+        const SlotPtrs S = st.s[B.slot];
+        uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
+        const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+        for (uint64_t i = gtid; i < B.n; i += stride) {
+            u32x2 pr = __builtin_nontemporal_load(pairs + i);
+            const uint32_t hip = pr.x, oip = pr.y;
+            const uint32_t q = ldc_bit(oip, c);
+            for (uint32_t r = 0; r < c.lr; ++r) {
+                uint32_t bit = ldca_bit(r, ldc_col(hip, r, c), q, c);
+                global_or(S.ldca + (bit >> 5), 1u << (bit & 31u));
+            }
+            if (sampled(oip, c)) {
+                const uint32_t b = se_bit(oip, c);
+                for (uint32_t r = 0; r < c.sr; ++r) {
+                    uint32_t bit = seav_byte(hip, r, c) * 8u + b;
+                    if (SEAV_LDS)
+                        atomicOr(&lds[bit >> 5], 1u << (bit & 31u));
+                    else
+                        global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
+                }
+            }
+        }
+    }
+    if (SEAV_LDS) {
+        // OR the workgroup's SEAV copy into the sketch; untouched words cost nothing.
+        __syncthreads();
+        uint32_t *seav_w = reinterpret_cast<uint32_t *>(st.s[0].seav);
+        for (uint32_t w = threadIdx.x; w < lds_words; w += blockDim.x) {
+            uint32_t v = lds[w];
+            if (v) global_or(seav_w + w, v);
+        }
+    }
+}
+
+hipError_t launch_scan_direct(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
+                              uint32_t block, uint32_t grid, bool seav_lds, hipStream_t s) {
+    BatchTable bt{};
+    SlotTable st{};
+    if (n_batches > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_batches; ++i) bt.b[i] = batches[i];
+    bt.n = n_batches;
+    for (int i = 0; i < kMaxGroup; ++i) st.s[i] = slots[i];
+    if (seav_lds) {
+        uint32_t words = (uint32_t)((c.seav_bytes + 3) / 4);
+        hipLaunchKernelGGL(k_scan_direct<true>, dim3(grid), dim3(block), words * 4u, s, c, bt, st, words);
+    } else {
+        hipLaunchKernelGGL(k_scan_direct<false>, dim3(grid), dim3(block), 0, s, c, bt, st, 0u);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------ sliding scan
+// Every bit the discrete scan would set receives the slice's stamp.  All writers of one slice
+// store the same value, and slices are ordered by the stream, so plain stores suffice.
+__global__ __launch_bounds__(1024) void k_scan_stamp(Consts c, BatchTable bt, SlotTable st, uint32_t stamp) {
+    const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint16_t v = (uint16_t)stamp;
+    for (uint32_t bi = 0; bi < bt.n; ++bi) {
+        const BatchDesc B = bt.b[bi];
+        const SlotPtrs S = st.s[B.slot];
+        const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+        for (uint64_t i = gtid; i < B.n; i += stride) {
+            u32x2 pr = __builtin_nontemporal_load(pairs + i);
+            const uint32_t hip = pr.x, oip = pr.y;
+            const uint32_t q = ldc_bit(oip, c);
+            for (uint32_t r = 0; r < c.lr; ++r) S.ldca_ts[ldca_bit(r, ldc_col(hip, r, c), q, c)] = v;
+            if (sampled(oip, c)) {
+                const uint32_t b = se_bit(oip, c);
+                for (uint32_t r = 0; r < c.sr; ++r) S.seav_ts[(uint64_t)seav_byte(hip, r, c) * 8u + b] = v;
+            }
+        }
+    }
+}
+
+hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
+                             uint16_t stamp, uint32_t block, uint32_t grid, hipStream_t s) {
+    BatchTable bt{};
+    SlotTable st{};
+    if (n_batches > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_batches; ++i) bt.b[i] = batches[i];
+    bt.n = n_batches;
+    for (int i = 0; i < kMaxGroup; ++i) st.s[i] = slots[i];
+    hipLaunchKernelGGL(k_scan_stamp, dim3(grid), dim3(block), 0, s, c, bt, st, (uint32_t)stamp);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------ binned scan
+// Block-wide pass over the bucket counters: cl[b] = LDCA items, cs[b] = SEAV items of bucket b.
+// Afterwards cl[b] = first slot of bucket b in the tile's item list, cs[b] = first SEAV slot
+// (after the bucket's LDCA items), cl[nb] = total items.
+template <int BLOCK>
+__device__ void bucket_offsets(uint32_t *cl, uint32_t *cs, uint32_t nb, uint32_t *scratch) {
+    constexpr int NW = BLOCK / 64;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+    const uint32_t per = (nb + BLOCK - 1) / BLOCK;
+    const uint32_t beg = tid * per < nb ? tid * per : nb;
+    const uint32_t end = beg + per < nb ? beg + per : nb;
+    uint32_t local = 0;
+    for (uint32_t b = beg; b < end; ++b) local += cl[b] + cs[b];
+    uint32_t incl = local;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(incl, o, 64);
+        if ((int)lane >= o) incl += t;
+    }
+    if (lane == 63u) scratch[wid] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < NW; ++w) {
+            uint32_t t = scratch[w];
+            scratch[w] = run;
+            run += t;
+        }
+        scratch[NW] = run;
+    }
+    __syncthreads();
+    uint32_t run = scratch[wid] + incl - local;
+    for (uint32_t b = beg; b < end; ++b) {
+        uint32_t l = cl[b], s = cs[b];
+        cl[b] = run;
+        cs[b] = run + l;
+        run += l + s;
+    }
+    if (tid == 0) cl[nb] = scratch[NW];
+    __syncthreads();
+}
+
+template <int LR, int PPT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTable bt, SlotTable st,
+                                               uint32_t *__restrict__ items, uint32_t *__restrict__ meta) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t nb = g.nb;
+    uint32_t *cl = lds;                  // [nb + 1] LDCA counts, then offsets
+    uint32_t *cs = cl + (nb + 1);        // [nb + 1] SEAV counts, then cursors
+    uint32_t *stage = lds + ((2 * (nb + 1) + 3) & ~3u);  // [cap] bucket-major items (16-byte aligned)
+    uint32_t *samp = stage + g.cap;      // [2 * scap] sampled (hip, H2 bit)
+    uint32_t *misc = samp + 2 * g.scap;  // [0] sampled count, [1..] scan scratch
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tile = blockIdx.x;
+    uint32_t bi = 0;
+    while (bi + 1 < bt.n && bt.b[bi + 1].first_tile <= tile) ++bi;
+    const BatchDesc B = bt.b[bi];
+    const SlotPtrs S = st.s[B.slot];
+    const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
+    const uint32_t smask = (1u << g.S) - 1u;
+    const uint32_t seav_base = (uint32_t)c.ldca_bits;   // SEAV bits follow the LDCA bits
+
+    for (uint32_t i = tid; i < 2 * (nb + 1); i += BLOCK) cl[i] = 0;
+    if (tid == 0) misc[0] = 0;
+
+    const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+    u32x2 pr[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
+        if (idx < B.n)
+            pr[j] = __builtin_nontemporal_load(pairs + idx);
+        else
+            pr[j] = u32x2{0u, 0u};
+    }
+    __syncthreads();
+
+    uint32_t key[PPT * LR], pay[PPT * LR];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const bool valid = p0 + (uint64_t)j * BLOCK + tid < B.n;
+        const uint32_t hip = pr[j].x, oip = pr[j].y;
+        const uint32_t q = ldc_bit(oip, c);
+#pragma unroll
+        for (int r = 0; r < LR; ++r) {
+            uint32_t bit = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
+            uint32_t bkt = bit >> g.S;
+            uint32_t rank = valid ? atomicAdd(&cl[bkt], 1u) : 0u;
+            key[j * LR + r] = valid ? ((bkt << 16) | rank) : 0xFFFFFFFFu;
+            pay[j * LR + r] = bit & smask;
+        }
+        if (valid && sampled(oip, c)) {
+            const uint32_t b = se_bit(oip, c);
+            uint32_t e = atomicAdd(&misc[0], 1u);
+            if (e < g.scap) {
+                samp[2 * e] = hip;
+                samp[2 * e + 1] = b;
+            } else {
+                // more sampled pairs than the tile reserved: record them directly
+                uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
+                for (uint32_t r = 0; r < c.sr; ++r) {
+                    uint32_t bit = seav_byte(hip, r, c) * 8u + b;
+                    global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t ns = misc[0] < g.scap ? misc[0] : g.scap;
+    for (uint32_t e = tid; e < ns; e += BLOCK) {
+        const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
+        for (uint32_t r = 0; r < c.sr; ++r) {
+            uint32_t bit = seav_base + seav_byte(hip, r, c) * 8u + b;
+            atomicAdd(&cs[bit >> g.S], 1u);
+        }
+    }
+    __syncthreads();
+    bucket_offsets<BLOCK>(cl, cs, nb, misc + 1);
+
+#pragma unroll
+    for (int k = 0; k < PPT * LR; ++k) {
+        uint32_t kk = key[k];
+        if (kk != 0xFFFFFFFFu) stage[cl[kk >> 16] + (kk & 0xFFFFu)] = pay[k];
+    }
+    for (uint32_t e = tid; e < ns; e += BLOCK) {
+        const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
+        for (uint32_t r = 0; r < c.sr; ++r) {
+            uint32_t bit = seav_base + seav_byte(hip, r, c) * 8u + b;
+            uint32_t pos = atomicAdd(&cs[bit >> g.S], 1u);
+            stage[pos] = bit & smask;
+        }
+    }
+    __syncthreads();
+    // items are at most 21 bits (S <= 20): three per 64-bit word, item j in word j / 3
+    const uint32_t total = cl[nb];
+    uint64_t *out = reinterpret_cast<uint64_t *>(items + (uint64_t)tile * g.region);
+    const uint32_t n64 = (total + 2) / 3;
+    for (uint32_t i = tid; i < n64; i += BLOCK) {
+        const uint32_t j = 3 * i;
+        uint64_t v = stage[j];
+        if (j + 1 < total) v |= (uint64_t)stage[j + 1] << 21;
+        if (j + 2 < total) v |= (uint64_t)stage[j + 2] << 42;
+        out[i] = v;
+    }
+    uint32_t *mo = meta + (uint64_t)tile * (nb + 1);
+    for (uint32_t i = tid; i <= nb; i += BLOCK) mo[i] = cl[i];
+}
+
+template <int LR, int PPT, int BLOCK>
+static void launch_bin_t(const Consts &c, const BinGeometry &g, const BatchTable &bt, const SlotTable &st,
+                         uint32_t n_tiles, uint32_t *items, uint32_t *meta, hipStream_t s) {
+    hipLaunchKernelGGL((k_bin<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st, items, meta);
+}
+
+template <int LR>
+static hipError_t launch_bin_lr(const Consts &c, const BinGeometry &g, const BatchTable &bt, const SlotTable &st,
+                                uint32_t n_tiles, uint32_t *items, uint32_t *meta, hipStream_t s) {
+    const uint32_t ppt = g.tile_pairs / g.block;
+    if (g.block == 1024 && ppt == 16) launch_bin_t<LR, 16, 1024>(c, g, bt, st, n_tiles, items, meta, s);
+    else if (g.block == 1024 && ppt == 8) launch_bin_t<LR, 8, 1024>(c, g, bt, st, n_tiles, items, meta, s);
+    else if (g.block == 1024 && ppt == 4) launch_bin_t<LR, 4, 1024>(c, g, bt, st, n_tiles, items, meta, s);
+    else if (g.block == 512 && ppt == 16) launch_bin_t<LR, 16, 512>(c, g, bt, st, n_tiles, items, meta, s);
+    else if (g.block == 512 && ppt == 8) launch_bin_t<LR, 8, 512>(c, g, bt, st, n_tiles, items, meta, s);
+    else if (g.block == 512 && ppt == 4) launch_bin_t<LR, 4, 512>(c, g, bt, st, n_tiles, items, meta, s);
+    else if (g.block == 256 && ppt == 16) launch_bin_t<LR, 16, 256>(c, g, bt, st, n_tiles, items, meta, s);
+    else if (g.block == 256 && ppt == 8) launch_bin_t<LR, 8, 256>(c, g, bt, st, n_tiles, items, meta, s);
+    else return hipErrorInvalidConfiguration;
+    return hipGetLastError();
+}
+
+hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+                      uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s) {
+    BatchTable bt{};
+    SlotTable st{};
+    if (n_batches == 0 || n_batches > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_batches; ++i) bt.b[i] = batches[i];
+    bt.n = n_batches;
+    for (int i = 0; i < kMaxGroup; ++i) st.s[i] = slots[i];
+    switch (c.lr) {
+    case 1: return launch_bin_lr<1>(c, g, bt, st, n_tiles, items, meta, s);
+    case 2: return launch_bin_lr<2>(c, g, bt, st, n_tiles, items, meta, s);
+    case 3: return launch_bin_lr<3>(c, g, bt, st, n_tiles, items, meta, s);
+    case 4: return launch_bin_lr<4>(c, g, bt, st, n_tiles, items, meta, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// meta[rows][cols] -> metaT[cols][rows]
+__global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                   uint32_t rows, uint32_t cols) {
+    __shared__ uint32_t t[32][33];
+    const uint32_t bx = blockIdx.y * 32, by = blockIdx.x * 32;   // bx: column block, by: row block
+    const uint32_t tx = threadIdx.x & 31u, ty = threadIdx.x >> 5;   // 32 x 8
+    for (uint32_t k = ty; k < 32; k += 8) {
+        uint32_t r = by + k, col = bx + tx;
+        if (r < rows && col < cols) t[k][tx] = in[(uint64_t)r * cols + col];
+    }
+    __syncthreads();
+    for (uint32_t k = ty; k < 32; k += 8) {
+        uint32_t col = bx + k, r = by + tx;
+        if (r < rows && col < cols) out[(uint64_t)col * rows + r] = t[tx][k];
+    }
+}
+
+hipError_t launch_transpose(const uint32_t *meta, uint32_t *metaT, uint32_t rows, uint32_t cols, hipStream_t s) {
+    if (rows == 0 || cols == 0 || (cols + 31) / 32 > 65535u) return hipErrorInvalidValue;
+    dim3 grid((rows + 31) / 32, (cols + 31) / 32);
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, meta, metaT, rows, cols);
+    return hipGetLastError();
+}
+
+constexpr uint32_t kApplyChunk = 1024;
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_apply(BinGeometry g, ApplyTable at, const uint32_t *__restrict__ items,
+                                                 const uint32_t *__restrict__ metaT, uint32_t n_tiles) {
+    extern __shared__ uint32_t lds[];
+    constexpr uint32_t NW = BLOCK / 64;
+    constexpr uint32_t U = 8;   // tiles per wavefront per step: U segment loads in flight per lane
+    const uint32_t words = 1u << (g.S - 5);
+    uint32_t *bm = lds;
+    uint32_t *mbeg = bm + words;
+    uint32_t *mend = mbeg + kApplyChunk;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+    const uint32_t si = blockIdx.x / g.nb, b = blockIdx.x % g.nb;
+    const ApplySlot A = at.s[si];
+    uint32_t *dst = b < g.nb_ldca ? A.ldca + (uint64_t)b * words : A.seav_w + (uint64_t)(b - g.nb_ldca) * words;
+    // LDCA buckets of a fresh slot start from zero; SEAV buckets always start from the sketch
+    // (a tile with more sampled pairs than it staged records the rest there directly)
+    if (A.fresh && b < g.nb_ldca) {
+        for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = 0;
+    } else {
+        for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = dst[w];
+    }
+    const uint64_t *items64 = reinterpret_cast<const uint64_t *>(items);
+    const uint32_t region64 = g.region / 2;
+    for (uint32_t t0 = A.tile_lo; t0 < A.tile_hi; t0 += kApplyChunk) {
+        const uint32_t nt = A.tile_hi - t0 < kApplyChunk ? A.tile_hi - t0 : kApplyChunk;
+        __syncthreads();
+        for (uint32_t k = tid; k < nt; k += BLOCK) {
+            mbeg[k] = metaT[(uint64_t)b * n_tiles + t0 + k];
+            mend[k] = metaT[(uint64_t)(b + 1) * n_tiles + t0 + k];
+        }
+        __syncthreads();
+        for (uint32_t k0 = wid * U; k0 < nt; k0 += NW * U) {
+            uint32_t v[U];
+            bool ok[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t k = k0 + u;
+                ok[u] = false;
+                v[u] = 0;
+                if (k < nt) {
+                    const uint32_t j = mbeg[k] + lane;
+                    if (j < mend[k]) {
+                        const uint64_t w = items64[(uint64_t)(t0 + k) * region64 + j / 3];
+                        v[u] = (uint32_t)(w >> (21 * (j % 3))) & 0x1FFFFFu;
+                        ok[u] = true;
+                    }
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (ok[u]) atomicOr(&bm[v[u] >> 5], 1u << (v[u] & 31u));
+            // segments longer than one wavefront
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t k = k0 + u;
+                if (k >= nt) break;
+                const uint32_t end = mend[k];
+                for (uint32_t j = mbeg[k] + 64 + lane; j < end; j += 64) {
+                    const uint64_t w = items64[(uint64_t)(t0 + k) * region64 + j / 3];
+                    const uint32_t it = (uint32_t)(w >> (21 * (j % 3))) & 0x1FFFFFu;
+                    atomicOr(&bm[it >> 5], 1u << (it & 31u));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t words4 = words / 4;
+    if (words4) {
+        for (uint32_t w = tid; w < words4; w += BLOCK)
+            reinterpret_cast<u32x4 *>(dst)[w] = reinterpret_cast<const u32x4 *>(bm)[w];
+    } else {
+        for (uint32_t w = tid; w < words; w += BLOCK) dst[w] = bm[w];
+    }
+}
+
+hipError_t launch_apply(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
+                        const uint32_t *metaT, uint32_t n_tiles, uint32_t block, hipStream_t s) {
+    ApplyTable at{};
+    if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
+    uint32_t lds = ((1u << (g.S - 5)) + 2 * kApplyChunk) * 4u;
+    dim3 grid(n_slots * g.nb);
+    if (block == 1024) hipLaunchKernelGGL(k_apply<1024>, grid, dim3(1024), lds, s, g, at, items, metaT, n_tiles);
+    else if (block == 512) hipLaunchKernelGGL(k_apply<512>, grid, dim3(512), lds, s, g, at, items, metaT, n_tiles);
+    else if (block == 256) hipLaunchKernelGGL(k_apply<256>, grid, dim3(256), lds, s, g, at, items, metaT, n_tiles);
+    else return hipErrorInvalidConfiguration;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------ merge
+__global__ void k_or_merge(uint32_t *__restrict__ dst, SrcTable src, uint32_t n_src, uint64_t n_words) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n4 = n_words / 4;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n4; i += stride) {
+        u32x4 v = {0u, 0u, 0u, 0u};
+        for (uint32_t k = 0; k < n_src; ++k) v |= __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(src.p[k]) + i);
+        reinterpret_cast<u32x4 *>(dst)[i] = v;
+    }
+    for (uint64_t i = n4 * 4 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_words; i += stride) {
+        uint32_t v = 0;
+        for (uint32_t k = 0; k < n_src; ++k) v |= src.p[k][i];
+        dst[i] = v;
+    }
+}
+
+hipError_t launch_or_merge(uint32_t *dst, const uint32_t *const *srcp, uint32_t n_src, uint64_t n_words, hipStream_t s) {
+    SrcTable src{};
+    if (n_src == 0 || n_src > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_src; ++i) src.p[i] = srcp[i];
+    uint64_t blocks = (n_words / 4 + 255) / 256;
+    uint32_t grid = (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
+    hipLaunchKernelGGL(k_or_merge, dim3(grid), dim3(256), 0, s, dst, src, n_src, n_words);
+    return hipGetLastError();
+}
+
+__global__ void k_max_merge_u16(uint16_t *__restrict__ dst, SrcTable16 src, uint32_t n_src, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint16_t v = 0;
+        for (uint32_t k = 0; k < n_src; ++k) {
+            uint16_t t = src.p[k][i];
+            v = t > v ? t : v;
+        }
+        dst[i] = v;
+    }
+}
+
+hipError_t launch_max_merge_u16(uint16_t *dst, const uint16_t *const *srcp, uint32_t n_src, uint64_t n, hipStream_t s) {
+    SrcTable16 src{};
+    if (n_src == 0 || n_src > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_src; ++i) src.p[i] = srcp[i];
+    uint64_t blocks = (n + 255) / 256;
+    uint32_t grid = (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
+    hipLaunchKernelGGL(k_max_merge_u16, dim3(grid), dim3(256), 0, s, dst, src, n_src, n);
+    return hipGetLastError();
+}
+
+// Shift every stamp down by off; stamps at or below off (outside every future window) become 0.
+__global__ void k_renormalize_u16(uint16_t *__restrict__ p, uint64_t n, uint16_t off) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint16_t v = p[i];
+        p[i] = v > off ? (uint16_t)(v - off) : (uint16_t)0;
+    }
+}
+
+hipError_t launch_renormalize_u16(uint16_t *p, uint64_t n, uint16_t off, hipStream_t s) {
+    uint64_t blocks = (n + 255) / 256;
+    uint32_t grid = (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
+    hipLaunchKernelGGL(k_renormalize_u16, dim3(grid), dim3(256), 0, s, p, n, off);
+    return hipGetLastError();
+}
+
+// Bit view of stamps: bit j of word w is 1 iff ts[32 w + j] >= thr.
+__global__ void k_bit_view(const uint16_t *__restrict__ ts, uint64_t n_words, uint16_t thr, uint32_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < n_words; w += stride) {
+        uint32_t v = 0;
+        for (uint32_t j = 0; j < 32; ++j) v |= (ts[w * 32 + j] >= thr ? 1u : 0u) << j;
+        out[w] = v;
+    }
+}
+
+hipError_t launch_bit_view(const uint16_t *ts, uint64_t n_bits, uint16_t thr, uint32_t *out_words, hipStream_t s) {
+    uint64_t n_words = n_bits / 32;
+    uint64_t blocks = (n_words + 255) / 256;
+    uint32_t grid = (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
+    hipLaunchKernelGGL(k_bit_view, dim3(grid), dim3(256), 0, s, ts, n_words, thr, out_words);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------ end of window
+template <bool SLIDING>
+__device__ __forceinline__ uint32_t load_se(const CloseArgs &a, uint64_t byte) {
+    if (!SLIDING) return a.seav[byte];
+    const uint16_t *t = a.seav_ts + byte * 8;
+    uint32_t v = 0;
+    for (uint32_t j = 0; j < 8; ++j) v |= (t[j] >= a.thr ? 1u : 0u) << j;
+    return v;
+}
+
+template <bool SLIDING>
+__device__ __forceinline__ uint32_t load_ldc_word(const CloseArgs &a, uint64_t word) {
+    if (!SLIDING) return a.ldca[word];
+    const uint16_t *t = a.ldca_ts + word * 32;
+    uint32_t v = 0;
+    for (uint32_t j = 0; j < 32; ++j) v |= (t[j] >= a.thr ? 1u : 0u) << j;
+    return v;
+}
+
+// Orders LDS traffic between lanes of one wavefront (writes by some lanes, reads by others).
+__device__ __forceinline__ void wave_lds_sync() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ULDC of every queued candidate: AND of its LR LDCs, z0 = k - popcount; report if z0 <= z_theta.
+template <bool SLIDING>
+__device__ void filter_queue(const CloseArgs &a, const Consts &c, const uint32_t *queue, uint32_t qn, uint32_t lane) {
+    const uint32_t words = 1u << (c.log2k - 5);
+    for (uint32_t e = 0; e < qn; ++e) {
+        const uint32_t h = queue[e];
+        uint32_t ones = 0;
+        for (uint32_t w = lane; w < words; w += 64) {
+            uint32_t u = 0xFFFFFFFFu;
+            for (uint32_t r = 0; r < c.lr; ++r) {
+                uint64_t base = ((uint64_t)((r << c.log2lc) | ldc_col(h, r, c))) << (c.log2k - 5);
+                u &= load_ldc_word<SLIDING>(a, base + w);
+            }
+            ones += __popc(u);
+        }
+        ones = wave_sum(ones);
+        const uint32_t z0 = (1u << c.log2k) - ones;
+        if (lane == 0 && z0 <= c.z_theta) {
+            uint32_t slot = atomicAdd(&a.counters[0], 1u);
+            if (slot < a.rec_cap) {
+                a.rec[2 * slot] = h;
+                a.rec[2 * slot + 1] = z0;
+            }
+        }
+    }
+}
+
+template <bool SLIDING, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_close(Consts c, CloseArgs a) {
+    extern __shared__ uint32_t lds[];
+    constexpr uint32_t NW = BLOCK / 64;
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+    const uint32_t per_wave = c.sr * a.list_stride + a.qcap;
+    uint32_t *lists = lds + wid * per_wave;      // row i: entries (cell << 8 | SE value)
+    uint32_t *queue = lists + c.sr * a.list_stride;
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t lmask = (c.L == 32) ? 0xFFFFFFFFull : ((1ull << c.L) - 1ull);
+    uint32_t n_cand = 0;
+
+    for (uint32_t rp = blockIdx.x * NW + wid; rp < a.n_rp; rp += gridDim.x * NW) {
+        const uint64_t sea = (uint64_t)rp * c.sea_bytes;
+        uint32_t cnt[kMaxRows];
+        bool empty = false;
+        for (uint32_t i = 0; i < c.sr; ++i) {
+            const uint32_t cells = 1u << c.ibn[i];
+            uint32_t n_hot = 0;
+            for (uint32_t c0 = 0; c0 < cells; c0 += 64) {
+                const uint32_t cell = c0 + lane;
+                uint32_t v = cell < cells ? load_se<SLIDING>(a, sea + c.row_off[i] + cell) : 0u;
+                const bool hot = __popc(v) >= kSeHot;
+                const uint64_t bal = __ballot(hot);
+                if (hot) lists[i * a.list_stride + n_hot + __popcll(bal & lane_lt)] = (cell << 8) | v;
+                n_hot += (uint32_t)__popcll(bal);
+            }
+            cnt[i] = n_hot;
+            if (n_hot == 0) {
+                empty = true;
+                break;
+            }
+        }
+        if (empty) continue;
+        wave_lds_sync();
+        uint64_t total = 1;
+        for (uint32_t i = 0; i < c.sr; ++i) total *= cnt[i];
+        uint32_t qn = 0;
+        if (total <= lmask + 1ull) {
+            // the product CIS of the hot lists (Section 3.2), one tuple per lane
+            for (uint64_t u0 = 0; u0 < total; u0 += 64) {
+                const uint64_t u = u0 + lane;
+                bool cand = false;
+                uint32_t h = 0;
+                if (u < total) {
+                    uint64_t rem = u;
+                    uint32_t lp = 0, seu = 0xFFu;
+                    uint32_t ci[kMaxRows];
+                    for (uint32_t i = 0; i < c.sr; ++i) {
+                        uint32_t d = (uint32_t)(rem % cnt[i]);
+                        rem /= cnt[i];
+                        uint32_t e = lists[i * a.list_stride + d];
+                        ci[i] = e >> 8;
+                        seu &= e & 0xFFu;
+                        lp |= row_bits_in_lp(ci[i], c.isb[i], c.L);
+                    }
+                    // Eq. 3: the rebuilt LP must give back every row index (overlap bits agree)
+                    bool ok = __popc(seu) >= kSeHot;
+                    for (uint32_t i = 0; i < c.sr; ++i) ok = ok && (row_index(lp, c.isb[i], c.ibn[i], c.L) == ci[i]);
+                    if (ok) {
+                        cand = true;
+                        h = (uint32_t)(((uint64_t)lp << c.r) | rp);
+                    }
+                }
+                const uint64_t bal = __ballot(cand);
+                if (cand) queue[qn + __popcll(bal & lane_lt)] = h;
+                qn += (uint32_t)__popcll(bal);
+                if (qn + 64 > a.qcap) {
+                    wave_lds_sync();
+                    filter_queue<SLIDING>(a, c, queue, qn, lane);
+                    n_cand += qn;
+                    qn = 0;
+                }
+            }
+        } else {
+            // more tuples than hosts in this SEA: test every LP directly (the candidate definition)
+            for (uint64_t l0 = 0; l0 <= lmask; l0 += 64) {
+                const uint64_t l = l0 + lane;
+                bool cand = false;
+                if (l <= lmask) {
+                    uint32_t seu = 0xFFu;
+                    for (uint32_t i = 0; i < c.sr; ++i)
+                        seu &= load_se<SLIDING>(a, sea + c.row_off[i] + row_index((uint32_t)l, c.isb[i], c.ibn[i], c.L));
+                    cand = __popc(seu) >= kSeHot;
+                }
+                const uint64_t bal = __ballot(cand);
+                if (cand) queue[qn + __popcll(bal & lane_lt)] = (uint32_t)((l << c.r) | rp);
+                qn += (uint32_t)__popcll(bal);
+                if (qn + 64 > a.qcap) {
+                    wave_lds_sync();
+                    filter_queue<SLIDING>(a, c, queue, qn, lane);
+                    n_cand += qn;
+                    qn = 0;
+                }
+            }
+        }
+        wave_lds_sync();
+        filter_queue<SLIDING>(a, c, queue, qn, lane);
+        n_cand += qn;
+        wave_lds_sync();
+    }
+    if (lane == 0 && n_cand) atomicAdd(&a.counters[1], n_cand);
+}
+
+hipError_t launch_close(const Consts &c, const CloseArgs &a, bool sliding, uint32_t block, uint32_t grid, hipStream_t s) {
+    uint32_t lds = (block / 64) * (c.sr * a.list_stride + a.qcap) * 4u;
+    if (block == 256) {
+        if (sliding) hipLaunchKernelGGL((k_close<true, 256>), dim3(grid), dim3(256), lds, s, c, a);
+        else hipLaunchKernelGGL((k_close<false, 256>), dim3(grid), dim3(256), lds, s, c, a);
+    } else if (block == 128) {
+        if (sliding) hipLaunchKernelGGL((k_close<true, 128>), dim3(grid), dim3(128), lds, s, c, a);
+        else hipLaunchKernelGGL((k_close<false, 128>), dim3(grid), dim3(128), lds, s, c, a);
+    } else if (block == 64) {
+        if (sliding) hipLaunchKernelGGL((k_close<true, 64>), dim3(grid), dim3(64), lds, s, c, a);
+        else hipLaunchKernelGGL((k_close<false, 64>), dim3(grid), dim3(64), lds, s, c, a);
+    } else {
+        return hipErrorInvalidConfiguration;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace spd

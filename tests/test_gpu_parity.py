@@ -1,0 +1,331 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Sketch bits (SEAV bytes and LDCA words) and the reported super points (ip, z0, est, flags) must
+be identical to the oracle's on the same seeded inputs.  The cases cover both scan kernels
+(direct atomics and LDS-binned), tiny tiles that give many buckets and ragged tails, every row
+count the binned kernel supports, router merges, window resets, import/export, edge inputs,
+saturated SEAs (the brute-force branch of the end-of-window kernel), the sliding window, and the
+full-size 1,000,000-pair and 64 Mi-pair windows.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth_traffic as st
+from gpu_util import (assert_same_report, assert_same_sketch, heavy_hosts, log, oracle_sketch, random_pairs,
+                      set_tuning, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1901_07306_amd as spd  # noqa: E402
+
+DIRECT = dict(direct_max_pairs=1 << 62)
+BINNED_SMALL = dict(direct_max_pairs=0, tile_pairs=2048, bucket_bits=12, bin_block=512, apply_block=256)
+BINNED_DEFAULT = dict(direct_max_pairs=0)
+
+
+def detector(mp, n_routers=1, isb=None, ibn=None, **tune):
+    det = spd.Detector(spd.params_from(mp, isb, ibn), n_routers=n_routers)
+    if tune:
+        set_tuning(det, **tune)
+    return det
+
+
+PARAMS = {
+    "tiny_r20_sr3": st.MethodParams(theta=256, r=20, sr=3, a=1, log2k=10, lr=2, log2lc=6, hash_seed=7),
+    "plain_1m": st.CONFIGS["plain_1m"].params,
+    "lr1_sr2": st.MethodParams(theta=1024, r=10, sr=2, a=3, log2k=12, lr=1, log2lc=10, hash_seed=11),
+    "lr3_sr5": st.MethodParams(theta=512, r=12, sr=5, a=2, log2k=11, lr=3, log2lc=9, hash_seed=13),
+    "lr4_sr4": st.MethodParams(theta=2048, r=8, sr=4, a=2, log2k=13, lr=4, log2lc=7, hash_seed=17),
+}
+
+
+@pytest.mark.parametrize("pname", list(PARAMS))
+@pytest.mark.parametrize("mode", ["direct", "binned_small", "binned_default"])
+def test_scan_and_close_parity(pname, mode):
+    mp = PARAMS[pname]
+    log(f"case params={pname} mode={mode}")
+    tune = {"direct": DIRECT, "binned_small": BINNED_SMALL, "binned_default": BINNED_DEFAULT}[mode]
+    rng = np.random.default_rng(hash((pname, mode)) % (1 << 32))
+    heavy, _ = heavy_hosts(rng, 8, 3000, noise=150_001)   # ragged: not a multiple of any tile
+    det = detector(mp, **tune)
+    try:
+        # three uneven batches into one window
+        cuts = [0, 1, 70_001, len(heavy)]
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            det.scan(0, to_dev(heavy[a:b]))
+        ref = oracle_sketch(mp, heavy)
+        assert_same_sketch(det, 0, ref, f"{pname}/{mode}")
+        got = det.close_window(0)
+        assert_same_report(got, ref.detect(), f"{pname}/{mode}")
+        # the window was reset: an empty window reports nothing and exports zeros
+        seav, ldca = det.export(0)
+        assert not seav.any() and not ldca.any()
+        assert len(det.close_window(0)) == 0
+    finally:
+        det.close()
+
+
+def test_empty_single_and_extreme_ips():
+    mp = PARAMS["plain_1m"]
+    log("case empty/single/extreme")
+    det = detector(mp, **DIRECT)
+    try:
+        det.scan(0, to_dev(np.zeros((0, 2), np.uint32)))
+        assert not det.export(0)[1].any()
+        pairs = np.array([[0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [0, 0xFFFFFFFF], [0xFFFFFFFF, 0]], np.uint32)
+        det.scan(0, to_dev(pairs[:1]))
+        det.scan(0, to_dev(pairs[1:]))
+        assert_same_sketch(det, 0, oracle_sketch(mp, pairs), "extreme ips")
+    finally:
+        det.close()
+
+
+def test_oip_whose_h1_is_zero_is_sampled():
+    """lsb(0) = 32 >= tau: choose the H1 addend so that H1(x0) = 0 exactly and check parity."""
+    base = PARAMS["tiny_r20_sr3"]
+    x0 = 0x12345678
+    mul, add = base.hashes()
+    add[0] = (-(mul[0] * x0)) % (1 << 64)
+    assert oracle.hash32(x0, mul[0], add[0], 32) == 0
+    p = spd.make_params(base.theta, base.r, base.sr, base.a, base.log2k, base.lr, base.log2lc, mul, add)
+    pairs = np.array([[0xCAFEBABE, x0]], np.uint32)
+    for tune in (DIRECT, BINNED_SMALL):
+        det = spd.Detector(p)
+        set_tuning(det, **tune)
+        try:
+            det.scan(0, to_dev(pairs))
+            op = oracle.params(base)
+            for j in range(3 + base.lr):
+                op.mul[j], op.add[j] = mul[j], add[j]
+            ref = oracle.Sketch(op).scan(pairs)
+            assert ref.seav.any()          # sampled
+            assert_same_sketch(det, 0, ref, "h1=0")
+        finally:
+            det.close()
+
+
+@pytest.mark.parametrize("mode", ["direct", "binned_small"])
+def test_routers_fused_batches_and_merge(mode):
+    mp = PARAMS["tiny_r20_sr3"].replace(theta=512)
+    log(f"case routers mode={mode}")
+    tune = DIRECT if mode == "direct" else BINNED_SMALL
+    rng = np.random.default_rng(5)
+    R = 5
+    det = detector(mp, n_routers=R, **tune)
+    try:
+        heavy, _ = heavy_hosts(rng, 10, 2000, noise=60_000)
+        owner = rng.integers(0, R, size=len(heavy))
+        per = [heavy[owner == r] for r in range(R)]
+        batches = []
+        for r in range(R):
+            cuts = np.sort(rng.integers(0, len(per[r]), size=3))
+            cuts = [0, *cuts.tolist(), len(per[r])]
+            for a, b in zip(cuts[:-1], cuts[1:]):
+                batches.append((r, to_dev(per[r][a:b])))
+        order = rng.permutation(len(batches))
+        det.scan_batches([batches[i] for i in order])
+        refs = [oracle_sketch(mp, per[r]) for r in range(R)]
+        for r in range(R):
+            assert_same_sketch(det, r, refs[r], f"router {r}")
+        det.merge([3, 1, 4, 0, 2, 1])            # any order, duplicates ignored
+        glob = oracle_sketch(mp, heavy)
+        assert_same_sketch(det, spd.GLOBAL, glob, "merged")
+        assert_same_report(det.close_window(spd.GLOBAL), glob.detect(), "global close")
+        # merging a subset == the oracle on that subset (a router dropped at close)
+        det.merge([0, 2])
+        sub = oracle_sketch(mp, np.concatenate([per[0], per[2]]))
+        assert_same_sketch(det, spd.GLOBAL, sub, "subset merge")
+        # per-router close reports that router's own detection and resets only it
+        assert_same_report(det.close_window(1), refs[1].detect(), "router close")
+        assert not det.export(1)[1].any()
+        assert_same_sketch(det, 2, refs[2], "router 2 untouched")
+    finally:
+        det.close()
+
+
+def test_import_export_roundtrip_and_determinism():
+    mp = PARAMS["plain_1m"]
+    rng = np.random.default_rng(9)
+    heavy, _ = heavy_hosts(rng, 12, 2500, noise=100_000)
+    ref = oracle_sketch(mp, heavy)
+    det = detector(mp, n_routers=2)
+    try:
+        det.import_(1, ref.seav, ref.ldca)
+        assert_same_sketch(det, 1, ref, "imported")
+        assert_same_report(det.close_window(1), ref.detect(), "close after import")
+        for _ in range(2):   # same bits on repeated runs
+            det.scan(0, to_dev(heavy))
+            assert_same_sketch(det, 0, ref, "repeat")
+            det.close_window(0)
+    finally:
+        det.close()
+
+
+def test_saturated_sea_uses_brute_force_branch():
+    """SEAs where every cell is hot: the tuple product exceeds 2^L, so the end-of-window kernel
+    tests every LP of the SEA instead; the report must still equal the oracle's."""
+    mp = st.MethodParams(theta=64, r=20, sr=4, a=1, log2k=9, lr=2, log2lc=8, hash_seed=23)
+    rng = np.random.default_rng(31)
+    rps = np.array([5, 77, 4000], np.uint32)
+    n = 60_000
+    lp = rng.integers(0, 1 << 12, size=n, dtype=np.uint64).astype(np.uint32)
+    src = (lp << np.uint32(20)) | rps[rng.integers(0, len(rps), size=n)]
+    dst = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    pairs = np.stack([src, dst], axis=1)
+    ref = oracle_sketch(mp, pairs)
+    cand = ref.candidates()
+    assert len(cand) > 3 * 1000
+    det = detector(mp, **DIRECT)
+    try:
+        det.scan(0, to_dev(pairs))
+        assert_same_sketch(det, 0, ref, "saturated")
+        got = det.close_window(0)
+        assert_same_report(got, ref.detect(), "saturated close")
+        assert det.stats.candidates_last == len(cand)
+    finally:
+        det.close()
+
+
+def test_many_reports_grow_record_buffer():
+    """More super points than the initial device record buffer (65536) holds."""
+    mp = st.MethodParams(theta=8, r=16, sr=4, a=2, log2k=6, lr=2, log2lc=16, hash_seed=41)
+    rng = np.random.default_rng(43)
+    pairs, hosts = heavy_hosts(rng, 90_000, 24)
+    ref = oracle_sketch(mp, pairs)
+    want = ref.detect()
+    assert len(want) > 65536
+    det = detector(mp, direct_max_pairs=0)
+    try:
+        det.scan(0, to_dev(pairs))
+        got = det.close_window(0, cap=200_000)
+        assert_same_report(got, want, "many reports")
+        with pytest.raises(spd.SpdError):
+            det.scan(0, to_dev(pairs))
+            det.close_window(0, cap=10)
+    finally:
+        det.close()
+
+
+def test_error_paths():
+    mp = PARAMS["plain_1m"]
+    det = detector(mp, n_routers=2)
+    try:
+        x = to_dev(np.zeros((10, 2), np.uint32))
+        with pytest.raises(spd.SpdError) as e:
+            det.scan(2, x)
+        assert e.value.status == spd.SPD_E_STATE
+        with pytest.raises(spd.SpdError) as e:
+            det.slide()
+        assert e.value.status == spd.SPD_E_STATE
+        with pytest.raises(spd.SpdError) as e:
+            det.close_window(7)
+        assert e.value.status == spd.SPD_E_STATE
+        # misaligned pair pointer (4 bytes past an 8-byte boundary)
+        lib = spd.lib()
+        st_ = lib.spd_scan(det.ctx, 0, x.data_ptr() + 4, 1, None)
+        assert st_ == spd.SPD_E_INVALID
+    finally:
+        det.close()
+    # HBM budget: the sketches alone exceed it
+    with pytest.raises(spd.SpdError) as e:
+        spd.Detector(spd.params_from(st.CONFIGS["plain_64m"].params), n_routers=4, hbm_budget_bytes=100 << 20)
+    assert e.value.status == spd.SPD_E_NOMEM
+
+
+# ------------------------------------------------------------------------------ sliding window
+@pytest.mark.parametrize("mode", ["one_router", "merged"])
+def test_sliding_window_parity(mode):
+    K = 4
+    mp = st.MethodParams(theta=256, r=12, sr=4, a=2, log2k=10, lr=2, log2lc=8, window_slices=K, hash_seed=51)
+    log(f"case sliding {mode}")
+    rng = np.random.default_rng(53)
+    R = 1 if mode == "one_router" else 3
+    det = detector(mp, n_routers=R, direct_max_pairs=0)
+    sl = [oracle.SlidingSketch(oracle.params(mp), K) for _ in range(R)]
+    slices = []
+    try:
+        for t in range(11):
+            if t:
+                det.slide()
+            pairs, _ = heavy_hosts(rng, 3, int(rng.integers(100, 400)), noise=20_000 + t)
+            owner = rng.integers(0, R, size=len(pairs))
+            for r in range(R):
+                det.scan(r, to_dev(pairs[owner == r]))
+                sl[r].scan_slice(pairs[owner == r], t)
+            slices.append(pairs)
+            assert spd.spd_current_slice(det.ctx) == t
+            if mode == "one_router":
+                ts_seav, ts_ldca = det.export_stamps(0)
+                np.testing.assert_array_equal(ts_seav, sl[0].seav_ts)
+                np.testing.assert_array_equal(ts_ldca, sl[0].ldca_ts)
+                view = sl[0].bit_view(t)
+                assert_same_sketch(det, 0, view, f"slice {t}")
+                assert_same_report(det.close_window(0), view.detect(), f"slice {t} close")
+            else:
+                det.merge(list(range(R)))
+                union = oracle_sketch(mp, np.concatenate(slices[max(0, t - K + 1): t + 1]))
+                assert_same_sketch(det, spd.GLOBAL, union, f"merged slice {t}")
+                assert_same_report(det.close_window(spd.GLOBAL), union.detect(), f"merged close {t}")
+    finally:
+        det.close()
+
+
+# ------------------------------------------------------------------------------ full size
+def test_plain_1m_full_window():
+    w = st.CONFIGS["plain_1m"]
+    log("case plain_1m full")
+    win = st.gen_plain(w)
+    ref = oracle_sketch(w.params, win.pairs[0])
+    for tune in (DIRECT, BINNED_DEFAULT):
+        det = detector(w.params, **tune)
+        try:
+            det.scan(0, to_dev(win.pairs[0]))
+            assert_same_sketch(det, 0, ref, "plain_1m")
+            got = det.close_window(0)
+            assert_same_report(got, ref.detect(), "plain_1m")
+            assert sorted(got["ip"].tolist()) == sorted(win.planted_ips.tolist())
+        finally:
+            det.close()
+
+
+def test_plain_64m_full_window():
+    w = st.CONFIGS["plain_64m"]
+    log("case plain_64m full: generating")
+    win = st.gen_plain(w)
+    log("case plain_64m full: oracle")
+    ref = oracle_sketch(w.params, win.pairs[0])
+    want = ref.detect()
+    log("case plain_64m full: gpu (default tuning, the configuration the benchmark times)")
+    det = detector(w.params)
+    try:
+        det.scan(0, to_dev(win.pairs[0]))
+        assert_same_sketch(det, 0, ref, "plain_64m")
+        got = det.close_window(0)
+        assert_same_report(got, want, "plain_64m")
+        assert len(got) >= 490   # sanity: (nearly) all 500 planted hosts are reported
+    finally:
+        det.close()
+
+
+def test_many_batches_one_call_binned():
+    """More batches in one fused call than one launch takes: the call is split into launch groups
+    and later groups must OR into the slots the earlier ones wrote."""
+    mp = PARAMS["plain_1m"]
+    rng = np.random.default_rng(61)
+    pairs, _ = heavy_hosts(rng, 6, 2200, noise=90_000)
+    cuts = np.sort(rng.choice(np.arange(1, len(pairs)), size=70, replace=False))
+    parts = np.split(pairs, cuts)
+    owner = [0 if i % 3 else 1 for i in range(len(parts))]
+    det = detector(mp, n_routers=2, **BINNED_SMALL)
+    try:
+        det.scan_batches([(o, to_dev(p)) for o, p in zip(owner, parts)])
+        for r in range(2):
+            mine = np.concatenate([p for o, p in zip(owner, parts) if o == r])
+            assert_same_sketch(det, r, oracle_sketch(mp, mine), f"router {r}")
+    finally:
+        det.close()
