@@ -94,6 +94,62 @@ def run_detector(spd, torch, params, x, steps, warmup, tune):
     return elapsed, close_ms, window_ms, prof, rec, stats
 
 
+def bench_serving(spd, torch, np, st, capacity_pps, windows_per_router, load, log_fn):
+    """The serving loop on the 16-router workload: batches of log-uniform size in [4Ki, 4Mi] pairs,
+    Poisson arrivals at `load` x capacity_pps, a window closed every 64Mi pairs per router.  Router
+    r's window w replays pool window (r + w) mod 4 of plain_64m-shaped traffic (1000 planted super
+    points spread over the pool).  Returns throughput, window latencies and admission figures."""
+    w = st.CONFIGS["serving_16r"]
+    R, W = w.n_routers, w.n_packets
+    pool = []
+    for k in range(4):
+        g = st.gen_plain(st.scaled(w, n_planted=w.n_planted // 4, seed=w.seed + k))
+        pool.append(torch.from_numpy(g.pairs[0].view(np.int32)).to("cuda"))
+    rng = np.random.default_rng(w.seed)
+    per_router = []
+    for r in range(R):
+        seq = []
+        for wi in range(windows_per_router):
+            src = pool[(r + wi) % 4]
+            cuts = st.split_batches(W, rng, 4096, 4 << 20)
+            seq += [src[a:b] for a, b in zip(cuts[:-1], cuts[1:])]
+        per_router.append(seq)
+    n_batches = sum(len(q) for q in per_router)
+    total = R * windows_per_router * W
+    mean = total / n_batches
+    rate = load * capacity_pps / mean          # batches per second over all routers
+    times = np.cumsum(rng.exponential(1.0 / rate, size=n_batches))
+    times -= times[0]
+    cursor = [0] * R
+    routers, tensors = [], []
+    for i in range(n_batches):
+        live = [r for r in range(R) if cursor[r] < len(per_router[r])]
+        r = live[int(rng.integers(0, len(live)))]
+        routers.append(r)
+        tensors.append(per_router[r][cursor[r]])
+        cursor[r] += 1
+    srv = spd.Server(spd.params_from(w.params), n_routers=R, window_pairs=W, hbm_budget_bytes=2 << 30,
+                     max_group_pairs=64 << 20, use_graphs=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    srv.replay(times, routers, tensors)
+    lat = []
+    for _ in range(R * windows_per_router):
+        got = srv.next(timeout_ms=120000)
+        if got is None:
+            raise RuntimeError("serving: a window did not finish")
+        lat.append(got[0]["latency_ms"])
+    el = time.perf_counter() - t0
+    stats = srv.stats
+    srv.close()
+    log_fn(f"serving load {load}: {total / el / 1e9:.1f} Gpairs/s, p50 {pct(lat, 50):.2f} ms, p99 {pct(lat, 99):.2f} ms")
+    return {"offered_load": load, "offered_pairs_per_s": load * capacity_pps, "value": total / el,
+            "unit": "packets/s", "routers": R, "windows": R * windows_per_router, "pairs": total,
+            "batches": n_batches, "window_latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99),
+                                                        "max": max(lat)},
+            "slots": stats["slots"], "admission_waits": stats["admission_waits"], "groups": stats["groups"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +157,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=5, help="steps for the plain per-batch kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="short run for rocprofv3 counter collection: 2 windows + one 512 MiB copy for scaling")
+    ap.add_argument("--serving-windows", type=int, default=1, help="windows per router in the serving run (0: skip)")
+    ap.add_argument("--serving-loads", default="0.5,1.0", help="offered loads, fractions of the measured capacity")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -129,6 +189,17 @@ def main() -> int:
     n = x.shape[0]
     params = spd.params_from(w.params)
 
+    if args.pmc_run:
+        det = spd.Detector(params)
+        for _ in range(2):
+            det.scan(0, x)
+            det.close_window(0)
+        y = x.clone()          # plain copy kernel of known size: reads and writes n * 8 bytes
+        torch.cuda.synchronize()
+        det.close()
+        log(f"pmc run done: copy of {n * 8} bytes, checksum {int(y[-1, 0])}")
+        return 0
+
     # the library's default path (binned scan) -- the headline value
     log(f"timing default scan: {args.warmup} warmup + {args.steps} steps")
     el, close_ms, window_ms, prof, rec, stats = run_detector(spd, torch, params, x, args.steps, args.warmup, {})
@@ -138,14 +209,16 @@ def main() -> int:
     dom = max(kinds, key=lambda k: kinds[k][1])
     dom_launches, dom_ms = kinds[dom]
     avg_ms = dom_ms / dom_launches
-    alg_bytes = {"bin": BYTES_PER_PAIR * n, "direct": BYTES_PER_PAIR * n}.get(dom)
-    if alg_bytes is None:
-        raise RuntimeError(f"unexpected dominant kernel {dom}")
+    # every scan kernel launch covers all n pairs of the step: 8 B of algorithmic traffic per pair
+    if dom not in ("bin", "transpose", "apply", "direct", "fill") or dom_launches != args.steps:
+        raise RuntimeError(f"unexpected dominant kernel {dom} ({dom_launches} launches)")
+    alg_bytes = BYTES_PER_PAIR * n
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     scan_kinds = ("bin", "transpose", "apply", "fill", "direct")
     scan_ms = sum(kinds.get(k, (0, 0.0))[1] for k in scan_kinds) / args.steps
     close_dev_ms = kinds.get("close", (0, 0.0))[1] / max(1, kinds.get("close", (1, 0))[0])
     traffic = measured_traffic()
+    log("device ms per step: " + ", ".join(f"{k} {v[1] / args.steps:.3f}" for k, v in kinds.items()))
 
     # the plain per-batch kernel: one thread per pair, global atomicOr into the sketches
     log(f"timing plain scan: 1 warmup + {args.plain_steps} steps")
@@ -205,6 +278,11 @@ def main() -> int:
         "batched_over_plain": value / plain_value,
         "gpu": torch.cuda.get_device_name(0),
     }
+
+    if args.serving_windows > 0:
+        log("serving loop: 16 routers")
+        out["serving"] = [bench_serving(spd, torch, np, st, value, args.serving_windows, float(ld), log)
+                          for ld in args.serving_loads.split(",")]
 
     if not args.no_cpu_baseline:
         import oracle

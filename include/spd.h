@@ -40,6 +40,7 @@ typedef int32_t spd_status;
 #define SPD_E_HIP (-3)        /* HIP runtime error; spd_last_error() has its text */
 #define SPD_E_TRUNCATED (-4)  /* output capacity too small; *n_out holds the required count */
 #define SPD_E_STATE (-5)      /* call not valid in the context's current state (e.g. bad router) */
+#define SPD_E_AGAIN (-6)      /* serving loop: no finished window within the timeout */
 
 #define SPD_MAX_ROWS 8        /* largest SR and LR */
 #define SPD_GLOBAL (-1)       /* target id of the merged (global) sketch */
@@ -101,6 +102,8 @@ typedef struct spd_tuning {
     uint32_t direct_grid_per_cu; /* direct scan: workgroups per compute unit */
     uint32_t seav_lds;         /* direct scan: 1 = keep a per-workgroup LDS copy of the SEAV when it fits */
     uint32_t close_block;      /* end-of-window kernel: threads per workgroup */
+    uint64_t launch_pairs;     /* binned scan: at most this many pairs per bin/apply launch (0: no limit);
+                                  smaller launches keep their items resident in the Infinity Cache */
 } spd_tuning;
 
 typedef struct spd_stats {
@@ -198,6 +201,84 @@ spd_status spd_get_stats(const spd_ctx *ctx, spd_stats *out);
 
 const char *spd_strerror(spd_status s);
 const char *spd_last_error(const spd_ctx *ctx);
+
+/* ------------------------------------------------------------------------------------------
+ * Serving loop.  Routers submit batches of pairs as they arrive; a scheduler thread keeps every
+ * open router window in a device slot, admits windows while slots fit the HBM budget (others
+ * wait), fuses whatever batches are pending, from any routers and of any sizes, into one scan
+ * launch group, and closes a window when its router has seen window_pairs pairs (a batch that
+ * crosses the boundary is split) or when a batch is submitted with SPD_SUBMIT_CLOSE.  Closes run
+ * on their own stream, replayed from a hipGraph captured per slot, and overlap later scans.  A
+ * window's result equals the result of scanning its pairs alone (Sections 3-4 are order-free).
+ * ------------------------------------------------------------------------------------------ */
+typedef struct spd_server spd_server;
+
+#define SPD_SUBMIT_CLOSE 1u    /* close the router's window after this batch */
+
+typedef struct spd_server_config {
+    uint32_t n_routers;
+    uint32_t max_slots;            /* upper bound on open windows (0: as many as the budget allows) */
+    uint64_t window_pairs;         /* close a router's window every this many pairs (0: on request only) */
+    uint64_t hbm_budget_bytes;     /* device memory for slots and scratch (0: 4 GiB) */
+    uint64_t max_group_pairs;      /* fused launch: at most this many pairs (0: 64 Mi) */
+    uint32_t max_group_batches;    /* fused launch: at most this many batches (0: 32) */
+    uint32_t use_graphs;           /* 1: replay each slot's end-of-window work from a hipGraph */
+} spd_server_config;
+
+typedef struct spd_window_result {
+    uint32_t router;
+    uint32_t window;               /* index of the window within its router, from 0 */
+    uint64_t pairs;                /* pairs recorded in the window */
+    double latency_ms;             /* submission of the batch that completed the window -> result on host */
+    uint32_t n_super;              /* super points reported (the first cap are copied out) */
+    uint32_t reserved;
+} spd_window_result;
+
+typedef struct spd_server_stats {
+    uint64_t batches;
+    uint64_t pairs;
+    uint64_t groups;               /* fused scan launches */
+    uint64_t windows;              /* windows closed */
+    uint64_t admission_waits;      /* times a router waited for a free slot */
+    uint32_t slots;                /* window slots that fit the budget */
+    uint32_t max_open;             /* most windows open at once */
+} spd_server_stats;
+
+/* Start a serving loop with its own scheduler thread and streams on the current device. */
+spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, spd_server **out);
+
+/* Hand over one batch (device pointer; must stay valid until its window has been reported).
+ * Returns at once. */
+spd_status spd_server_submit(spd_server *srv, uint32_t router, const uint32_t *pairs_dev, uint64_t n_pairs,
+                             uint32_t flags);
+
+/* Next finished window: header in *hdr, its super points (sorted by ip) in out_host[0..cap).
+ * Waits up to timeout_ms (negative: forever); SPD_E_AGAIN if none finished in time. */
+spd_status spd_server_next(spd_server *srv, spd_window_result *hdr, spd_superpoint *out_host, uint32_t cap,
+                           int32_t timeout_ms);
+
+/* One arrival of a replayed traffic schedule. */
+typedef struct spd_arrival {
+    double t_s;                    /* arrival time in seconds from the start of the replay */
+    uint32_t router;
+    uint32_t flags;                /* SPD_SUBMIT_CLOSE or 0 */
+    const uint32_t *pairs_dev;
+    uint64_t n_pairs;
+} spd_arrival;
+
+/* Submit a schedule of arrivals (sorted by t_s) from the calling thread, each at its time: a
+ * native load generator for Poisson-like router traffic.  Returns the seconds it took. */
+spd_status spd_server_replay(spd_server *srv, const spd_arrival *sched, uint64_t n, double *elapsed_s);
+
+/* Wait until every submitted batch has been scanned and every requested close has finished. */
+spd_status spd_server_drain(spd_server *srv);
+
+spd_status spd_server_get_stats(spd_server *srv, spd_server_stats *out);
+spd_status spd_server_set_tuning(spd_server *srv, const spd_tuning *t);
+const char *spd_server_last_error(spd_server *srv);
+
+/* Stop the scheduler (pending work is finished first) and release everything. */
+void spd_server_destroy(spd_server *srv);
 
 #ifdef __cplusplus
 }

@@ -50,7 +50,7 @@ class SpdBatch(ctypes.Structure):
 class SpdTuning(ctypes.Structure):
     _fields_ = [("direct_max_pairs", u64), ("bucket_bits", u32), ("tile_pairs", u32), ("bin_block", u32),
                 ("apply_block", u32), ("direct_block", u32), ("direct_grid_per_cu", u32), ("seav_lds", u32),
-                ("close_block", u32)]
+                ("close_block", u32), ("launch_pairs", u64)]
 
 
 class SpdStats(ctypes.Structure):
@@ -65,12 +65,37 @@ class SpdProfile(ctypes.Structure):
     _fields_ = [("launches", u64 * 8), ("total_ms", ctypes.c_double * 8)]
 
 
+class SpdServerConfig(ctypes.Structure):
+    _fields_ = [("n_routers", u32), ("max_slots", u32), ("window_pairs", u64), ("hbm_budget_bytes", u64),
+                ("max_group_pairs", u64), ("max_group_batches", u32), ("use_graphs", u32)]
+
+
+class SpdWindowResult(ctypes.Structure):
+    _fields_ = [("router", u32), ("window", u32), ("pairs", u64), ("latency_ms", ctypes.c_double),
+                ("n_super", u32), ("reserved", u32)]
+
+
+class SpdArrival(ctypes.Structure):
+    _fields_ = [("t_s", ctypes.c_double), ("router", u32), ("flags", u32), ("pairs_dev", ctypes.c_void_p),
+                ("n_pairs", u64)]
+
+
+class SpdServerStats(ctypes.Structure):
+    _fields_ = [("batches", u64), ("pairs", u64), ("groups", u64), ("windows", u64), ("admission_waits", u64),
+                ("slots", u32), ("max_open", u32)]
+
+
 RECORD = np.dtype([("ip", "<u4"), ("z0", "<u4"), ("est", "<u4"), ("flags", "<u4")])
 
 EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_batches", "spd_merge",
             "spd_close_window", "spd_slide", "spd_export", "spd_import", "spd_export_stamps",
             "spd_current_slice", "spd_get_tuning", "spd_set_tuning", "spd_get_stats", "spd_strerror",
-            "spd_last_error", "spd_profile_enable", "spd_get_profile"]
+            "spd_last_error", "spd_profile_enable", "spd_get_profile", "spd_server_create", "spd_server_submit",
+            "spd_server_next", "spd_server_drain", "spd_server_get_stats", "spd_server_set_tuning",
+            "spd_server_last_error", "spd_server_destroy", "spd_server_replay"]
+
+SPD_E_AGAIN = -6
+SPD_SUBMIT_CLOSE = 1
 
 
 class SpdError(RuntimeError):
@@ -129,6 +154,15 @@ def lib(require_torch: bool = True) -> ctypes.CDLL:
         "spd_get_stats": (i32, [vp, P(SpdStats)]),
         "spd_profile_enable": (i32, [vp, u32]),
         "spd_get_profile": (i32, [vp, P(SpdProfile)]),
+        "spd_server_create": (i32, [P(SpdParams), P(SpdServerConfig), P(vp)]),
+        "spd_server_submit": (i32, [vp, u32, vp, u64, u32]),
+        "spd_server_next": (i32, [vp, P(SpdWindowResult), P(SpdSuperpoint), u32, i32]),
+        "spd_server_drain": (i32, [vp]),
+        "spd_server_get_stats": (i32, [vp, P(SpdServerStats)]),
+        "spd_server_set_tuning": (i32, [vp, P(SpdTuning)]),
+        "spd_server_last_error": (ctypes.c_char_p, [vp]),
+        "spd_server_destroy": (None, [vp]),
+        "spd_server_replay": (i32, [vp, P(SpdArrival), u64, P(ctypes.c_double)]),
         "spd_strerror": (ctypes.c_char_p, [i32]),
         "spd_last_error": (ctypes.c_char_p, [vp]),
     }
@@ -357,3 +391,80 @@ class Detector:
     @property
     def stats(self) -> SpdStats:
         return spd_get_stats(self.ctx)
+
+
+# ------------------------------------------------------------------------------ serving loop
+class Server:
+    """The serving loop of libspd: submit batches per router as they arrive, collect finished
+    windows with next()."""
+
+    def __init__(self, params: SpdParams, n_routers: int, window_pairs: int = 0, hbm_budget_bytes: int = 0,
+                 max_slots: int = 0, max_group_pairs: int = 0, max_group_batches: int = 0, use_graphs: bool = True):
+        self.params = params
+        cfg = SpdServerConfig(n_routers, max_slots, window_pairs, hbm_budget_bytes, max_group_pairs,
+                              max_group_batches, 1 if use_graphs else 0)
+        h = ctypes.c_void_p()
+        st = lib().spd_server_create(ctypes.byref(params), ctypes.byref(cfg), ctypes.byref(h))
+        if st != SPD_OK:
+            raise SpdError(st, "spd_server_create failed")
+        self.h = h.value
+        self._keep = []   # device tensors handed over, kept alive until the server is closed
+
+    def _check(self, st):
+        if st != SPD_OK:
+            raise SpdError(st, lib().spd_server_last_error(self.h).decode() or lib().spd_strerror(st).decode())
+
+    def submit(self, router: int, pairs, close: bool = False, keep: bool = True):
+        ptr, n = _pairs_ptr(pairs)
+        if keep:
+            self._keep.append(pairs)
+        self._check(lib().spd_server_submit(self.h, router, ptr or None, n, SPD_SUBMIT_CLOSE if close else 0))
+
+    def next(self, timeout_ms: int = -1, cap: int = 1 << 16):
+        """(header dict, structured array of super points) or None on timeout."""
+        hdr = SpdWindowResult()
+        out = (SpdSuperpoint * max(1, cap))()
+        st = lib().spd_server_next(self.h, ctypes.byref(hdr), out, cap, timeout_ms)
+        if st == SPD_E_AGAIN:
+            return None
+        self._check(st)
+        sp = np.frombuffer(out, dtype=RECORD, count=max(1, cap))[: hdr.n_super].copy()
+        return dict(router=hdr.router, window=hdr.window, pairs=hdr.pairs, latency_ms=hdr.latency_ms,
+                    n_super=hdr.n_super), sp
+
+    def replay(self, times, routers, tensors, flags=None) -> float:
+        """Submit tensors[i] for routers[i] at times[i] seconds (sorted) from a native loop."""
+        n = len(times)
+        arr = (SpdArrival * max(1, n))()
+        for i in range(n):
+            ptr, cnt = _pairs_ptr(tensors[i])
+            arr[i] = SpdArrival(float(times[i]), int(routers[i]), int(flags[i]) if flags is not None else 0,
+                                ptr or None, cnt)
+            self._keep.append(tensors[i])
+        el = ctypes.c_double(0.0)
+        self._check(lib().spd_server_replay(self.h, arr, n, ctypes.byref(el)))
+        return el.value
+
+    def drain(self):
+        self._check(lib().spd_server_drain(self.h))
+
+    @property
+    def stats(self) -> dict:
+        s = SpdServerStats()
+        self._check(lib().spd_server_get_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in SpdServerStats._fields_}
+
+    def set_tuning(self, t: SpdTuning):
+        self._check(lib().spd_server_set_tuning(self.h, ctypes.byref(t)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().spd_server_destroy(self.h)
+            self.h = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

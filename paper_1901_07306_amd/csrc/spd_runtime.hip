@@ -26,6 +26,29 @@ struct Slot {
     bool fresh = true;           // logically all zero; device memory not yet cleared
 };
 
+struct WorkItem {
+    Slot *slot;
+    const uint32_t *pairs;
+    uint64_t n;
+};
+
+constexpr uint32_t kRecInit = 65536;   // device records per close buffer, grown on demand
+constexpr uint32_t kRecChunk = 4096;   // records copied back together with the counters
+
+// Device and pinned host buffers of one end-of-window pass.
+struct CloseBuf {
+    uint32_t *rec = nullptr;          // device (ip, z0) records
+    uint32_t rec_cap = 0;
+    uint32_t *counters = nullptr;     // device [0] reported, [1] candidates
+    uint32_t *h_counters = nullptr;   // pinned
+    uint32_t *h_rec = nullptr;        // pinned
+    uint32_t h_rec_cap = 0;
+    bool empty = false;               // the slot was fresh: nothing was launched
+    hipGraphExec_t graph = nullptr;   // captured close of graph_slot
+    const Slot *graph_slot = nullptr;
+    const uint32_t *graph_rec = nullptr;
+};
+
 }  // namespace
 
 struct spd_ctx {
@@ -41,6 +64,7 @@ struct spd_ctx {
     uint32_t K = 0;
     uint32_t slice = 0;
     uint64_t seav_alloc = 0;     // padded SEAV bytes per slot
+    uint64_t ldca_bytes = 0;     // LDCA bytes per slot, rounded up to 256
     uint64_t slot_bytes = 0;
     std::vector<Slot> slots;     // routers, then the global sketch
     uint32_t *items = nullptr;
@@ -48,12 +72,7 @@ struct spd_ctx {
     uint32_t *meta = nullptr;
     uint32_t *metaT = nullptr;
     uint64_t meta_words = 0;
-    uint32_t *rec = nullptr;
-    uint32_t rec_cap = 0;
-    uint32_t *counters = nullptr;   // device [4]
-    uint32_t *h_counters = nullptr; // pinned host [4]
-    uint32_t *h_rec = nullptr;      // pinned host records
-    uint32_t h_rec_cap = 0;
+    CloseBuf cbuf;                  // end-of-window buffers of spd_close_window
     uint32_t *view = nullptr;       // sliding export: bit view words
     uint64_t view_words = 0;
     std::vector<uint32_t> est;      // Eq. 4 estimate for every z0 in [0, k]
@@ -185,6 +204,7 @@ void default_tuning(spd_tuning *t) {
     t->direct_grid_per_cu = 8;
     t->seav_lds = 0;
     t->close_block = 256;
+    t->launch_pairs = 0;
 }
 
 void order_stream(spd_ctx *ctx, hipStream_t s) {
@@ -366,109 +386,103 @@ spd_status ensure_scratch(spd_ctx *ctx, uint64_t items_words, uint64_t meta_word
     return SPD_OK;
 }
 
-// Record a group of batches whose routers are distinct-or-repeated; batches sorted by router.
-spd_status scan_group(spd_ctx *ctx, std::vector<spd_batch> &bs, hipStream_t s) {
-    std::stable_sort(bs.begin(), bs.end(), [](const spd_batch &x, const spd_batch &y) { return x.router < y.router; });
+// Record batches into slots.  Batches of one slot are kept together so that each slot's tiles are
+// one contiguous range of the binned launch.
+spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
+    std::stable_sort(ws.begin(), ws.end(), [](const WorkItem &x, const WorkItem &y) {
+        return std::less<Slot *>()(x.slot, y.slot);
+    });
     uint64_t total = 0;
-    std::vector<uint32_t> routers;
-    for (auto &b : bs) {
-        total += b.n_pairs;
-        if (routers.empty() || routers.back() != b.router) routers.push_back(b.router);
+    std::vector<Slot *> slots;
+    for (auto &w : ws) {
+        total += w.n;
+        if (slots.empty() || slots.back() != w.slot) slots.push_back(w.slot);
     }
     if (total == 0) return SPD_OK;
-    if (ctx->sliding) {
-        // time stamps of the current slice, plain stores
-        for (size_t i0 = 0; i0 < bs.size(); i0 += kMaxGroup) {
+    // direct-style launches (sliding stamps, or small batches): groups of kMaxGroup batches
+    auto direct_launch = [&](bool stamp) -> spd_status {
+        for (size_t i0 = 0; i0 < ws.size(); i0 += kMaxGroup) {
             BatchDesc bd[kMaxGroup];
             SlotPtrs sp[kMaxGroup] = {};
             uint32_t nbd = 0, nsl = 0;
             uint64_t n = 0;
-            std::vector<uint32_t> seen;
-            for (size_t i = i0; i < std::min(bs.size(), i0 + kMaxGroup); ++i) {
-                auto it = std::find(seen.begin(), seen.end(), bs[i].router);
+            std::vector<Slot *> seen;
+            for (size_t i = i0; i < std::min(ws.size(), i0 + kMaxGroup); ++i) {
+                auto it = std::find(seen.begin(), seen.end(), ws[i].slot);
                 uint32_t si = (uint32_t)(it - seen.begin());
                 if (it == seen.end()) {
-                    seen.push_back(bs[i].router);
-                    sp[nsl++] = ptrs_of(ctx->slots[bs[i].router]);
+                    seen.push_back(ws[i].slot);
+                    sp[nsl++] = ptrs_of(*ws[i].slot);
                 }
-                bd[nbd++] = BatchDesc{bs[i].pairs_dev, bs[i].n_pairs, 0, si};
-                n = std::max(n, bs[i].n_pairs);
+                bd[nbd++] = BatchDesc{ws[i].pairs, ws[i].n, 0, si};
+                n = std::max(n, ws[i].n);
             }
             uint32_t block = ctx->tune.direct_block;
             uint64_t want = (n + block - 1) / block;
-            uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)ctx->tune.direct_grid_per_cu * ctx->n_cu));
-            ProfScope ps(ctx, SPD_K_STAMP, s);
-            SPD_HIP(ctx, launch_scan_stamp(ctx->c, bd, nbd, sp, (uint16_t)(ctx->slice + 1), block, grid, s));
-        }
-        ctx->stats.pairs_scanned += total;
-        ctx->stats.direct_launches++;
-        return SPD_OK;
-    }
-    BinGeometry g{};
-    const bool binned = total > ctx->tune.direct_max_pairs && ctx->p.lr <= 4 && bin_geometry(ctx, &g);
-    std::vector<uint32_t> fresh_routers;
-    for (uint32_t r : routers) {
-        Slot &sl = ctx->slots[r];
-        if (!sl.fresh) continue;
-        spd_status st = binned ? clear_seav(ctx, sl, s) : clear_slot(ctx, sl, s);
-        if (st) return st;
-        if (binned) fresh_routers.push_back(r);
-        sl.fresh = false;
-    }
-    if (!binned) {
-        for (size_t i0 = 0; i0 < bs.size(); i0 += kMaxGroup) {
-            BatchDesc bd[kMaxGroup];
-            SlotPtrs sp[kMaxGroup] = {};
-            uint32_t nbd = 0, nsl = 0;
-            uint64_t n = 0;
-            std::vector<uint32_t> seen;
-            for (size_t i = i0; i < std::min(bs.size(), i0 + kMaxGroup); ++i) {
-                auto it = std::find(seen.begin(), seen.end(), bs[i].router);
-                uint32_t si = (uint32_t)(it - seen.begin());
-                if (it == seen.end()) {
-                    seen.push_back(bs[i].router);
-                    sp[nsl++] = ptrs_of(ctx->slots[bs[i].router]);
-                }
-                bd[nbd++] = BatchDesc{bs[i].pairs_dev, bs[i].n_pairs, 0, si};
-                n = std::max(n, bs[i].n_pairs);
+            uint32_t grid = (uint32_t)std::max<uint64_t>(
+                1, std::min<uint64_t>(want, (uint64_t)ctx->tune.direct_grid_per_cu * ctx->n_cu));
+            if (stamp) {
+                ProfScope ps(ctx, SPD_K_STAMP, s);
+                SPD_HIP(ctx, launch_scan_stamp(ctx->c, bd, nbd, sp, (uint16_t)(ctx->slice + 1), block, grid, s));
+            } else {
+                const bool lds = ctx->tune.seav_lds && nsl == 1 && ctx->d.seav_bytes <= 64 * 1024;
+                ProfScope ps(ctx, SPD_K_DIRECT, s);
+                SPD_HIP(ctx, launch_scan_direct(ctx->c, bd, nbd, sp, block, grid, lds, s));
             }
-            const bool lds = ctx->tune.seav_lds && nsl == 1 && ctx->d.seav_bytes <= 64 * 1024;
-            uint32_t block = ctx->tune.direct_block;
-            uint64_t want = (n + block - 1) / block;
-            uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)ctx->tune.direct_grid_per_cu * ctx->n_cu));
-            ProfScope ps(ctx, SPD_K_DIRECT, s);
-            SPD_HIP(ctx, launch_scan_direct(ctx->c, bd, nbd, sp, block, grid, lds, s));
             ctx->stats.direct_launches++;
         }
         ctx->stats.pairs_scanned += total;
         return SPD_OK;
+    };
+    if (ctx->sliding) return direct_launch(true);   // time stamps of the current slice, plain stores
+    BinGeometry g{};
+    const bool binned = total > ctx->tune.direct_max_pairs && ctx->p.lr <= 4 && bin_geometry(ctx, &g);
+    std::vector<Slot *> fresh_slots;
+    for (Slot *sl : slots) {
+        if (!sl->fresh) continue;
+        spd_status st = binned ? clear_seav(ctx, *sl, s) : clear_slot(ctx, *sl, s);
+        if (st) return st;
+        if (binned) fresh_slots.push_back(sl);
+        sl->fresh = false;
     }
-    // binned: groups of at most kMaxGroup batches (and routers)
+    if (!binned) return direct_launch(false);
+    // split batches larger than one launch may take
+    const uint64_t lp = ctx->tune.launch_pairs;
+    if (lp) {
+        std::vector<WorkItem> split;
+        for (auto &w : ws)
+            for (uint64_t a = 0; a < w.n; a += lp) split.push_back(WorkItem{w.slot, w.pairs + 2 * a, std::min(lp, w.n - a)});
+        ws.swap(split);
+    }
+    // binned: launch groups of at most kMaxGroup batches, kMaxGroup slots and launch_pairs pairs
     size_t i0 = 0;
-    while (i0 < bs.size()) {
+    while (i0 < ws.size()) {
         BatchDesc bd[kMaxGroup];
         SlotPtrs sp[kMaxGroup] = {};
         ApplySlot as[kMaxGroup] = {};
+        Slot *owner[kMaxGroup] = {};
         uint32_t nbd = 0, nsl = 0, tiles = 0;
+        uint64_t lpairs = 0;
         size_t i = i0;
-        for (; i < bs.size() && nbd < (uint32_t)kMaxGroup; ++i) {
-            const spd_batch &b = bs[i];
-            if (b.n_pairs == 0) continue;
-            if (nsl == 0 || as[nsl - 1].pad != b.router) {
+        for (; i < ws.size() && nbd < (uint32_t)kMaxGroup; ++i) {
+            const WorkItem &w = ws[i];
+            if (w.n == 0) continue;
+            if (lp && nbd && lpairs + w.n > lp) break;
+            lpairs += w.n;
+            if (nsl == 0 || owner[nsl - 1] != w.slot) {
                 if (nsl == (uint32_t)kMaxGroup) break;
-                Slot &sl = ctx->slots[b.router];
-                sp[nsl] = ptrs_of(sl);
-                as[nsl].ldca = sl.ldca;
-                as[nsl].seav_w = reinterpret_cast<uint32_t *>(sl.seav);
+                sp[nsl] = ptrs_of(*w.slot);
+                as[nsl].ldca = w.slot->ldca;
+                as[nsl].seav_w = reinterpret_cast<uint32_t *>(w.slot->seav);
                 as[nsl].tile_lo = tiles;
                 // a fresh slot's LDCA buckets are written from zero by this launch
-                as[nsl].fresh = std::find(fresh_routers.begin(), fresh_routers.end(), b.router) != fresh_routers.end();
-                as[nsl].pad = b.router;
+                as[nsl].fresh = std::find(fresh_slots.begin(), fresh_slots.end(), w.slot) != fresh_slots.end();
+                owner[nsl] = w.slot;
                 ++nsl;
             }
-            const uint64_t nt = (b.n_pairs + g.tile_pairs - 1) / g.tile_pairs;
+            const uint64_t nt = (w.n + g.tile_pairs - 1) / g.tile_pairs;
             if ((uint64_t)tiles + nt > 0x7FFFFFFFull) return fail(ctx, SPD_E_INVALID, "batch too large");
-            bd[nbd++] = BatchDesc{b.pairs_dev, b.n_pairs, tiles, nsl - 1};
+            bd[nbd++] = BatchDesc{w.pairs, w.n, tiles, nsl - 1};
             tiles += (uint32_t)nt;
             as[nsl - 1].tile_hi = tiles;
         }
@@ -490,33 +504,200 @@ spd_status scan_group(spd_ctx *ctx, std::vector<spd_batch> &bs, hipStream_t s) {
         }
         // later groups of the same call OR into these slots
         for (uint32_t k = 0; k < nsl; ++k)
-            fresh_routers.erase(std::remove(fresh_routers.begin(), fresh_routers.end(), as[k].pad), fresh_routers.end());
+            fresh_slots.erase(std::remove(fresh_slots.begin(), fresh_slots.end(), owner[k]), fresh_slots.end());
         ctx->stats.binned_launches++;
     }
     ctx->stats.pairs_scanned += total;
     return SPD_OK;
 }
 
-spd_status validate_batch(spd_ctx *ctx, const spd_batch &b) {
-    if (b.router >= ctx->n_routers) return fail(ctx, SPD_E_STATE, "router id out of range");
-    if (b.reserved != 0) return fail(ctx, SPD_E_INVALID, "spd_batch.reserved must be 0");
-    if (b.n_pairs && !b.pairs_dev) return fail(ctx, SPD_E_INVALID, "null pair buffer");
-    if (reinterpret_cast<uintptr_t>(b.pairs_dev) % 8) return fail(ctx, SPD_E_INVALID, "pair buffer must be 8-byte aligned");
-    if (b.n_pairs > (1ull << 40)) return fail(ctx, SPD_E_INVALID, "batch too large");
+// ------------------------------------------------------------------------------ end of window
+spd_status close_buf_init(spd_ctx *ctx, CloseBuf &cb) {
+    if (!cb.counters) {
+        spd_status st = dev_alloc(ctx, &cb.counters, 16);
+        if (st) return st;
+    }
+    if (!cb.rec) {
+        spd_status st = dev_alloc(ctx, &cb.rec, (uint64_t)kRecInit * 8);
+        if (st) return st;
+        cb.rec_cap = kRecInit;
+    }
+    if (!cb.h_counters) SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_counters, 16, hipHostMallocDefault));
+    if (!cb.h_rec) {
+        SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_rec, (uint64_t)kRecChunk * 8, hipHostMallocDefault));
+        cb.h_rec_cap = kRecChunk;
+    }
     return SPD_OK;
 }
 
-}  // namespace
+void close_buf_free(spd_ctx *ctx, CloseBuf &cb) {
+    if (cb.graph) (void)hipGraphExecDestroy(cb.graph);
+    cb.graph = nullptr;
+    dev_free(ctx, &cb.rec, (uint64_t)cb.rec_cap * 8);
+    dev_free(ctx, &cb.counters, 16);
+    if (cb.h_counters) (void)hipHostFree(cb.h_counters);
+    if (cb.h_rec) (void)hipHostFree(cb.h_rec);
+    cb.h_counters = nullptr;
+    cb.h_rec = nullptr;
+    cb.rec_cap = cb.h_rec_cap = 0;
+}
 
-// ==============================================================================================
-extern "C" {
+// Arguments and launch shape of the end-of-window kernel for one slot.
+spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArgs *a, uint32_t *block, uint32_t *grid) {
+    *a = CloseArgs{};
+    a->seav = sl.seav;
+    a->ldca = sl.ldca;
+    a->seav_ts = sl.seav_ts;
+    a->ldca_ts = sl.ldca_ts;
+    if (ctx->sliding) {
+        const int64_t lo = (int64_t)ctx->slice - (int64_t)ctx->K + 2;
+        a->thr = lo < 1 ? 1u : (uint32_t)lo;
+    }
+    a->counters = cb.counters;
+    a->rec = cb.rec;
+    a->rec_cap = cb.rec_cap;
+    a->n_rp = 1u << ctx->p.r;
+    uint32_t max_ibn = 0;
+    for (uint32_t i = 0; i < ctx->p.sr; ++i) max_ibn = std::max(max_ibn, ctx->d.ibn[i]);
+    a->list_stride = 1u << max_ibn;
+    a->qcap = 256;
+    uint32_t b = ctx->tune.close_block;
+    while (b > 64 && (b / 64) * (ctx->p.sr * a->list_stride + a->qcap) * 4ull > kMaxLds) b /= 2;
+    if ((b / 64) * (ctx->p.sr * a->list_stride + a->qcap) * 4ull > kMaxLds)
+        return fail(ctx, SPD_E_INVALID, "SEA rows too large for the end-of-window kernel");
+    const uint32_t waves = b / 64;
+    const uint64_t want = ((uint64_t)a->n_rp + waves - 1) / waves;
+    *block = b;
+    *grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)ctx->n_cu * 16));
+    return SPD_OK;
+}
 
-spd_status spd_derive(const spd_params *p, spd_derived *out) { return derive(p, out, nullptr); }
+// The device part of the end of window: clear the counters, run k_close, copy the counters and
+// the first kRecChunk records to pinned host memory.  Asynchronous on s.
+spd_status close_launch_ops(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStream_t s) {
+    CloseArgs a;
+    uint32_t block, grid;
+    spd_status st = close_args(ctx, sl, cb, &a, &block, &grid);
+    if (st) return st;
+    SPD_HIP(ctx, launch_fill_u32(cb.counters, 4, 0u, s));
+    {
+        ProfScope ps(ctx, SPD_K_CLOSE, s);
+        SPD_HIP(ctx, launch_close(ctx->c, a, ctx->sliding, block, grid, s));
+    }
+    SPD_HIP(ctx, hipMemcpyAsync(cb.h_counters, cb.counters, 16, hipMemcpyDeviceToHost, s));
+    SPD_HIP(ctx, hipMemcpyAsync(cb.h_rec, cb.rec, (uint64_t)std::min(cb.rec_cap, kRecChunk) * 8, hipMemcpyDeviceToHost, s));
+    return SPD_OK;
+}
 
-spd_status spd_create(const spd_params *p, uint32_t n_routers, uint64_t hbm_budget_bytes, spd_ctx **out) {
-    if (!out) return SPD_E_INVALID;
-    *out = nullptr;
-    if (n_routers < 1 || n_routers > 4096) return SPD_E_INVALID;
+spd_status close_launch(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStream_t s) {
+    cb.empty = !ctx->sliding && sl.fresh;
+    if (cb.empty) return SPD_OK;
+    spd_status st = close_buf_init(ctx, cb);
+    if (st) return st;
+    return close_launch_ops(ctx, sl, cb, s);
+}
+
+// Same device work replayed from a hipGraph captured once per (slot, buffer); discrete mode only.
+spd_status close_launch_graph(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStream_t s) {
+    cb.empty = sl.fresh;
+    if (cb.empty) return SPD_OK;
+    spd_status st = close_buf_init(ctx, cb);
+    if (st) return st;
+    if (!cb.graph || cb.graph_slot != &sl || cb.graph_rec != cb.rec) {
+        if (cb.graph) (void)hipGraphExecDestroy(cb.graph);
+        cb.graph = nullptr;
+        hipGraph_t g = nullptr;
+        const bool prof = ctx->prof_on;
+        ctx->prof_on = false;   // no event nodes inside the graph
+        SPD_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        spd_status cst = close_launch_ops(ctx, sl, cb, s);
+        hipError_t e = hipStreamEndCapture(s, &g);
+        ctx->prof_on = prof;
+        if (cst) {
+            if (g) (void)hipGraphDestroy(g);
+            return cst;
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&cb.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
+        cb.graph_slot = &sl;
+        cb.graph_rec = cb.rec;
+    }
+    ProfScope ps(ctx, SPD_K_CLOSE, s);
+    SPD_HIP(ctx, hipGraphLaunch(cb.graph, s));
+    return SPD_OK;
+}
+
+// Host part, after the launched work has completed: fetch records beyond the first chunk, grow
+// the record buffer and run again if it overflowed (the pass is deterministic), build the sorted
+// report with Eq. 4 estimates.  Discrete mode: the slot becomes fresh (next window from zero).
+spd_status close_finish(spd_ctx *ctx, Slot &sl, CloseBuf &cb, hipStream_t s, std::vector<spd_superpoint> *out) {
+    out->clear();
+    ctx->stats.closes++;
+    if (cb.empty) {
+        ctx->stats.candidates_last = 0;
+        ctx->stats.reported_last = 0;
+        return SPD_OK;
+    }
+    uint32_t n = cb.h_counters[0];
+    ctx->stats.candidates_last = cb.h_counters[1];
+    if (n > cb.rec_cap) {
+        dev_free(ctx, &cb.rec, (uint64_t)cb.rec_cap * 8);
+        cb.rec_cap = 0;
+        const uint32_t want = n + 1024;
+        spd_status st = dev_alloc(ctx, &cb.rec, (uint64_t)want * 8);
+        if (st) return st;
+        cb.rec_cap = want;
+        st = close_launch_ops(ctx, sl, cb, s);
+        if (st) return st;
+        SPD_HIP(ctx, hipStreamSynchronize(s));
+        n = cb.h_counters[0];
+    }
+    if (n > kRecChunk) {
+        if (n > cb.h_rec_cap) {
+            (void)hipHostFree(cb.h_rec);
+            cb.h_rec = nullptr;
+            cb.h_rec_cap = 0;
+            SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_rec, (uint64_t)n * 8, hipHostMallocDefault));
+            cb.h_rec_cap = n;
+        }
+        SPD_HIP(ctx, hipMemcpyAsync(cb.h_rec, cb.rec, (uint64_t)n * 8, hipMemcpyDeviceToHost, s));
+        SPD_HIP(ctx, hipStreamSynchronize(s));
+    }
+    out->resize(n);
+    const uint32_t kmax = 1u << ctx->p.log2k;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t z0 = cb.h_rec[2 * i + 1];
+        (*out)[i] = spd_superpoint{cb.h_rec[2 * i], z0, ctx->est[std::min(z0, kmax)], z0 == 0 ? 1u : 0u};
+    }
+    std::sort(out->begin(), out->end(), [](const spd_superpoint &x, const spd_superpoint &y) { return x.ip < y.ip; });
+    ctx->stats.reported_last = n;
+    if (!ctx->sliding) sl.fresh = true;   // the next window starts from zero
+    return SPD_OK;
+}
+
+// ------------------------------------------------------------------------------ contexts
+spd_status slot_alloc(spd_ctx *ctx, Slot &sl) {
+    spd_status st = dev_alloc(ctx, &sl.mem, ctx->slot_bytes);
+    if (st) return st;
+    const uint64_t ldca_bytes = ctx->ldca_bytes;
+    if (ctx->sliding) {
+        sl.ldca_ts = static_cast<uint16_t *>(sl.mem);
+        sl.seav_ts = sl.ldca_ts + ldca_bytes * 8;
+        SPD_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(sl.mem), ctx->slot_bytes / 4, 0u, nullptr));
+        sl.fresh = false;
+    } else {
+        sl.ldca = static_cast<uint32_t *>(sl.mem);
+        sl.seav = static_cast<uint8_t *>(sl.mem) + ldca_bytes;
+        sl.fresh = true;
+    }
+    return SPD_OK;
+}
+
+// A context with n_slots sketch slots; spd_create uses routers + the global sketch, the serving
+// loop allocates its own window slots.
+spd_status ctx_create(const spd_params *p, uint32_t n_routers, uint32_t n_slots, uint64_t budget, spd_ctx **out) {
     spd_ctx *ctx = new (std::nothrow) spd_ctx();
     if (!ctx) return SPD_E_NOMEM;
     std::string why;
@@ -527,7 +708,7 @@ spd_status spd_create(const spd_params *p, uint32_t n_routers, uint64_t hbm_budg
     }
     ctx->p = *p;
     ctx->n_routers = n_routers;
-    ctx->budget = hbm_budget_bytes;
+    ctx->budget = budget;
     ctx->sliding = p->window_slices > 0;
     ctx->K = p->window_slices;
     default_tuning(&ctx->tune);
@@ -563,6 +744,7 @@ spd_status spd_create(const spd_params *p, uint32_t n_routers, uint64_t hbm_budg
     c.z_theta = ctx->d.z_theta;
     c.ldca_bits = ctx->d.ldca_words * 32;
     c.seav_bytes = ctx->d.seav_bytes;
+    // Eq. 4 estimate for every z0, computed once in double
     ctx->est.resize((1u << p->log2k) + 1);
     const double k = std::ldexp(1.0, (int)p->log2k);
     for (uint32_t z = 0; z <= (1u << p->log2k); ++z)
@@ -570,33 +752,18 @@ spd_status spd_create(const spd_params *p, uint32_t n_routers, uint64_t hbm_budg
 
     DeviceGuard dg(ctx->device);
     ctx->seav_alloc = (ctx->d.seav_bytes + kSeavAlign - 1) / kSeavAlign * kSeavAlign;
-    const uint64_t ldca_bytes = (ctx->d.ldca_words * 4 + 255) / 256 * 256;   // SEAV starts 256-byte aligned
+    ctx->ldca_bytes = (ctx->d.ldca_words * 4 + 255) / 256 * 256;   // SEAV starts 256-byte aligned
     // sliding: one 16-bit stamp per bit
-    ctx->slot_bytes = ctx->sliding ? (ldca_bytes * 16 + ctx->seav_alloc * 16) : (ldca_bytes + ctx->seav_alloc);
-    ctx->slots.resize(n_routers + 1);
-    hipStream_t s0 = nullptr;
+    ctx->slot_bytes = ctx->sliding ? (ctx->ldca_bytes * 16 + ctx->seav_alloc * 16) : (ctx->ldca_bytes + ctx->seav_alloc);
+    ctx->slots.resize(n_slots);
     for (auto &sl : ctx->slots) {
-        st = dev_alloc(ctx, &sl.mem, ctx->slot_bytes);
+        st = slot_alloc(ctx, sl);
         if (st) {
             spd_destroy(ctx);
             return st;
         }
-        if (ctx->sliding) {
-            sl.ldca_ts = static_cast<uint16_t *>(sl.mem);
-            sl.seav_ts = sl.ldca_ts + ldca_bytes * 8;
-            if (launch_fill_u32(static_cast<uint32_t *>(sl.mem), ctx->slot_bytes / 4, 0u, s0) != hipSuccess) {
-                spd_destroy(ctx);
-                return SPD_E_HIP;
-            }
-            sl.fresh = false;
-        } else {
-            sl.ldca = static_cast<uint32_t *>(sl.mem);
-            sl.seav = static_cast<uint8_t *>(sl.mem) + ldca_bytes;
-            sl.fresh = true;
-        }
     }
-    if (dev_alloc(ctx, &ctx->counters, 16) || hipEventCreateWithFlags(&ctx->order_ev, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->h_counters, 16, hipHostMallocDefault) != hipSuccess) {
+    if (close_buf_init(ctx, ctx->cbuf) || hipEventCreateWithFlags(&ctx->order_ev, hipEventDisableTiming) != hipSuccess) {
         spd_destroy(ctx);
         return SPD_E_HIP;
     }
@@ -609,6 +776,29 @@ spd_status spd_create(const spd_params *p, uint32_t n_routers, uint64_t hbm_budg
     return SPD_OK;
 }
 
+spd_status validate_batch(spd_ctx *ctx, const spd_batch &b) {
+    if (b.router >= ctx->n_routers) return fail(ctx, SPD_E_STATE, "router id out of range");
+    if (b.reserved != 0) return fail(ctx, SPD_E_INVALID, "spd_batch.reserved must be 0");
+    if (b.n_pairs && !b.pairs_dev) return fail(ctx, SPD_E_INVALID, "null pair buffer");
+    if (reinterpret_cast<uintptr_t>(b.pairs_dev) % 8) return fail(ctx, SPD_E_INVALID, "pair buffer must be 8-byte aligned");
+    if (b.n_pairs > (1ull << 40)) return fail(ctx, SPD_E_INVALID, "batch too large");
+    return SPD_OK;
+}
+
+}  // namespace
+
+// ==============================================================================================
+extern "C" {
+
+spd_status spd_derive(const spd_params *p, spd_derived *out) { return derive(p, out, nullptr); }
+
+spd_status spd_create(const spd_params *p, uint32_t n_routers, uint64_t hbm_budget_bytes, spd_ctx **out) {
+    if (!out) return SPD_E_INVALID;
+    *out = nullptr;
+    if (n_routers < 1 || n_routers > 4096) return SPD_E_INVALID;
+    return ctx_create(p, n_routers, n_routers + 1, hbm_budget_bytes, out);
+}
+
 void spd_destroy(spd_ctx *ctx) {
     if (!ctx) return;
     {
@@ -618,11 +808,8 @@ void spd_destroy(spd_ctx *ctx) {
         dev_free(ctx, &ctx->items, ctx->items_words * 4);
         dev_free(ctx, &ctx->meta, ctx->meta_words * 4);
         dev_free(ctx, &ctx->metaT, ctx->meta_words * 4);
-        dev_free(ctx, &ctx->rec, (uint64_t)ctx->rec_cap * 8);
-        dev_free(ctx, &ctx->counters, 16);
+        close_buf_free(ctx, ctx->cbuf);
         dev_free(ctx, &ctx->view, ctx->view_words * 4);
-        if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
-        if (ctx->h_rec) (void)hipHostFree(ctx->h_rec);
         if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
         prof_harvest(ctx);
         for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
@@ -639,18 +826,18 @@ spd_status spd_scan(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_dev, ui
 spd_status spd_scan_batches(spd_ctx *ctx, const spd_batch *batches, uint32_t n_batches, void *stream) {
     if (!ctx) return SPD_E_INVALID;
     if (n_batches && !batches) return fail(ctx, SPD_E_INVALID, "null batch list");
-    std::vector<spd_batch> bs;
-    bs.reserve(n_batches);
+    std::vector<WorkItem> ws;
+    ws.reserve(n_batches);
     for (uint32_t i = 0; i < n_batches; ++i) {
         spd_status st = validate_batch(ctx, batches[i]);
         if (st) return st;
-        if (batches[i].n_pairs) bs.push_back(batches[i]);
+        if (batches[i].n_pairs) ws.push_back(WorkItem{&ctx->slots[batches[i].router], batches[i].pairs_dev, batches[i].n_pairs});
     }
-    if (bs.empty()) return SPD_OK;
+    if (ws.empty()) return SPD_OK;
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     order_stream(ctx, s);
-    return scan_group(ctx, bs, s);
+    return scan_work(ctx, ws, s);
 }
 
 spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *stream) {
@@ -703,83 +890,16 @@ spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_ho
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     order_stream(ctx, s);
-    ctx->stats.closes++;
-    if (!ctx->sliding && sl->fresh) {
-        ctx->stats.candidates_last = 0;
-        ctx->stats.reported_last = 0;
-        return SPD_OK;
-    }
-    CloseArgs a{};
-    a.seav = sl->seav;
-    a.ldca = sl->ldca;
-    a.seav_ts = sl->seav_ts;
-    a.ldca_ts = sl->ldca_ts;
-    if (ctx->sliding) {
-        const int64_t lo = (int64_t)ctx->slice - (int64_t)ctx->K + 2;
-        a.thr = lo < 1 ? 1u : (uint32_t)lo;
-    }
-    a.counters = ctx->counters;
-    a.n_rp = 1u << ctx->p.r;
-    uint32_t max_ibn = 0;
-    for (uint32_t i = 0; i < ctx->p.sr; ++i) max_ibn = std::max(max_ibn, ctx->d.ibn[i]);
-    a.list_stride = 1u << max_ibn;
-    a.qcap = 256;
-    uint32_t block = ctx->tune.close_block;
-    while (block > 64 && (block / 64) * (ctx->p.sr * a.list_stride + a.qcap) * 4ull > kMaxLds) block /= 2;
-    if ((block / 64) * (ctx->p.sr * a.list_stride + a.qcap) * 4ull > kMaxLds)
-        return fail(ctx, SPD_E_INVALID, "SEA rows too large for the end-of-window kernel");
-    const uint32_t waves = block / 64;
-    const uint64_t want = ((uint64_t)a.n_rp + waves - 1) / waves;
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)ctx->n_cu * 16));
-    if (ctx->rec_cap == 0) {
-        spd_status st = dev_alloc(ctx, &ctx->rec, 65536ull * 8);
-        if (st) return st;
-        ctx->rec_cap = 65536;
-    }
-    uint32_t n = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        a.rec = ctx->rec;
-        a.rec_cap = ctx->rec_cap;
-        SPD_HIP(ctx, launch_fill_u32(ctx->counters, 4, 0u, s));
-        {
-            ProfScope ps(ctx, SPD_K_CLOSE, s);
-            SPD_HIP(ctx, launch_close(ctx->c, a, ctx->sliding, block, grid, s));
-        }
-        SPD_HIP(ctx, hipMemcpyAsync(ctx->h_counters, ctx->counters, 16, hipMemcpyDeviceToHost, s));
-        SPD_HIP(ctx, hipStreamSynchronize(s));
-        n = ctx->h_counters[0];
-        ctx->stats.candidates_last = ctx->h_counters[1];
-        if (n <= ctx->rec_cap) break;
-        // more reports than the record buffer holds: grow it and run the (deterministic) pass again
-        dev_free(ctx, &ctx->rec, (uint64_t)ctx->rec_cap * 8);
-        ctx->rec_cap = 0;
-        uint32_t want_cap = n + 1024;
-        spd_status st = dev_alloc(ctx, &ctx->rec, (uint64_t)want_cap * 8);
-        if (st) return st;
-        ctx->rec_cap = want_cap;
-    }
-    if (n > ctx->h_rec_cap) {
-        if (ctx->h_rec) (void)hipHostFree(ctx->h_rec);
-        ctx->h_rec = nullptr;
-        ctx->h_rec_cap = 0;
-        SPD_HIP(ctx, hipHostMalloc((void **)&ctx->h_rec, (uint64_t)std::max<uint32_t>(n, 1024) * 8, hipHostMallocDefault));
-        ctx->h_rec_cap = std::max<uint32_t>(n, 1024);
-    }
-    if (n) {
-        SPD_HIP(ctx, hipMemcpyAsync(ctx->h_rec, ctx->rec, (uint64_t)n * 8, hipMemcpyDeviceToHost, s));
-        SPD_HIP(ctx, hipStreamSynchronize(s));
-    }
-    std::vector<spd_superpoint> res(n);
-    for (uint32_t i = 0; i < n; ++i) {
-        const uint32_t z0 = ctx->h_rec[2 * i + 1];
-        res[i] = spd_superpoint{ctx->h_rec[2 * i], z0, ctx->est[std::min<uint32_t>(z0, 1u << ctx->p.log2k)], z0 == 0 ? 1u : 0u};
-    }
-    std::sort(res.begin(), res.end(), [](const spd_superpoint &x, const spd_superpoint &y) { return x.ip < y.ip; });
+    std::vector<spd_superpoint> res;
+    spd_status st = close_launch(ctx, *sl, ctx->cbuf, s);
+    if (st) return st;
+    SPD_HIP(ctx, hipStreamSynchronize(s));
+    st = close_finish(ctx, *sl, ctx->cbuf, s, &res);
+    if (st) return st;
+    const uint32_t n = (uint32_t)res.size();
     const uint32_t w = std::min(n, cap);
     if (w) std::memcpy(out_host, res.data(), (size_t)w * sizeof(spd_superpoint));
     *n_out = n;
-    ctx->stats.reported_last = n;
-    if (!ctx->sliding) sl->fresh = true;   // the next window starts from zero
     return n > cap ? fail(ctx, SPD_E_TRUNCATED, "output capacity smaller than the number of super points") : SPD_OK;
 }
 
@@ -936,5 +1056,433 @@ const char *spd_strerror(spd_status s) {
 }
 
 const char *spd_last_error(const spd_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ==============================================================================================
+// Serving loop: continuous batching of many routers' batches over device window slots.
+// ==============================================================================================
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+
+namespace {
+using Clock = std::chrono::steady_clock;
+
+struct SrvPending {
+    const uint32_t *pairs;
+    uint64_t n;
+    uint32_t flags;
+    Clock::time_point t;
+};
+
+struct SrvRouter {
+    int slot = -1;                // open window's slot, -1 = none
+    uint64_t in_window = 0;       // pairs recorded in the open window
+    uint32_t window = 0;          // index of the open window
+    std::deque<SrvPending> q;
+    bool waiting = false;         // counted once per admission wait
+};
+
+struct SrvClosing {
+    int slot;
+    uint32_t router, window;
+    uint64_t pairs;
+    Clock::time_point t_req;
+    hipEvent_t done;
+};
+
+struct SrvResult {
+    spd_window_result hdr;
+    std::vector<spd_superpoint> sp;
+};
+}  // namespace
+
+struct spd_server {
+    spd_ctx *ctx = nullptr;       // method constants, kernels, scratch, profiler; its slots are the pool
+    spd_server_config cfg{};
+    std::vector<CloseBuf> cbs;    // one per slot (with its captured graph)
+    std::vector<int> free_slots;
+    std::vector<SrvRouter> routers;
+    std::deque<SrvClosing> closing;
+    std::deque<SrvResult> done;
+    std::vector<hipEvent_t> ev_pool;
+    hipStream_t scan_s = nullptr, close_s = nullptr;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    uint64_t queued = 0;          // batches submitted and not yet fully scanned
+    spd_server_stats st{};
+    spd_status fault = SPD_OK;    // first error seen by the scheduler
+    std::string err;
+    uint32_t rr = 0;              // round-robin start
+};
+
+namespace {
+
+hipEvent_t srv_event(spd_server *S) {
+    if (!S->ev_pool.empty()) {
+        hipEvent_t e = S->ev_pool.back();
+        S->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+void srv_fault(spd_server *S, spd_status st) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (!S->fault) {
+        S->fault = st;
+        S->err = S->ctx->err;
+    }
+    S->cv_done.notify_all();
+}
+
+// Finish every close whose device work is complete (or wait for the oldest if block is set).
+bool srv_reap(spd_server *S, bool block) {
+    bool any = false;
+    for (;;) {
+        SrvClosing c;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (S->closing.empty()) return any;
+            c = S->closing.front();
+        }
+        hipError_t q = block && !any ? hipEventSynchronize(c.done) : hipEventQuery(c.done);
+        if (q == hipErrorNotReady) return any;
+        if (q != hipSuccess) {
+            srv_fault(S, hip_fail(S->ctx, q, "close event"));
+            return any;
+        }
+        SrvResult res;
+        spd_status st = close_finish(S->ctx, S->ctx->slots[c.slot], S->cbs[c.slot], S->close_s, &res.sp);
+        if (st) {
+            srv_fault(S, st);
+            return any;
+        }
+        const double ms = std::chrono::duration<double, std::milli>(Clock::now() - c.t_req).count();
+        res.hdr = spd_window_result{c.router, c.window, c.pairs, ms, (uint32_t)res.sp.size(), 0};
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->closing.pop_front();
+            S->ev_pool.push_back(c.done);
+            S->free_slots.push_back(c.slot);
+            S->done.push_back(std::move(res));
+            S->st.windows++;
+        }
+        S->cv_done.notify_all();
+        S->cv_work.notify_all();
+        any = true;
+    }
+}
+
+struct SrvClose {
+    uint32_t router;
+    int slot;
+    uint32_t window;
+    uint64_t pairs;
+    Clock::time_point t_req;
+};
+
+void srv_loop(spd_server *S) {
+    DeviceGuard dg(S->ctx->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        // ---- admission: a router with pending batches and no open window takes a free slot
+        const uint32_t R = S->cfg.n_routers;
+        for (uint32_t k = 0; k < R; ++k) {
+            SrvRouter &r = S->routers[(S->rr + k) % R];
+            if (r.q.empty() || r.slot >= 0) continue;
+            if (S->free_slots.empty()) {
+                if (!r.waiting) S->st.admission_waits++;
+                r.waiting = true;
+                continue;
+            }
+            r.slot = S->free_slots.back();
+            S->free_slots.pop_back();
+            r.waiting = false;
+            uint32_t open = 0;
+            for (auto &x : S->routers) open += x.slot >= 0;
+            S->st.max_open = std::max(S->st.max_open, open);
+        }
+        // ---- one fused group from the routers that hold a slot, round robin
+        std::vector<WorkItem> group;
+        std::vector<SrvClose> closes;
+        std::vector<uint64_t> finished_batches;
+        uint64_t gp = 0;
+        for (uint32_t k = 0; k < R && gp < S->cfg.max_group_pairs && group.size() < S->cfg.max_group_batches; ++k) {
+            const uint32_t ri = (S->rr + k) % R;
+            SrvRouter &r = S->routers[ri];
+            if (r.slot < 0) continue;
+            while (!r.q.empty() && gp < S->cfg.max_group_pairs && group.size() < S->cfg.max_group_batches) {
+                SrvPending &b = r.q.front();
+                uint64_t room = S->cfg.window_pairs ? S->cfg.window_pairs - r.in_window : UINT64_MAX;
+                uint64_t take = std::min(b.n, room);
+                if (take) group.push_back(WorkItem{&S->ctx->slots[r.slot], b.pairs, take});
+                gp += take;
+                r.in_window += take;
+                const bool whole = take == b.n;
+                const bool boundary = S->cfg.window_pairs && r.in_window == S->cfg.window_pairs;
+                const bool close = boundary || (whole && (b.flags & SPD_SUBMIT_CLOSE));
+                const Clock::time_point t = b.t;
+                if (whole) {
+                    r.q.pop_front();
+                    S->queued--;
+                } else {
+                    b.pairs += 2 * take;
+                    b.n -= take;
+                }
+                if (close) {
+                    closes.push_back(SrvClose{ri, r.slot, r.window, r.in_window, t});
+                    r.slot = -1;
+                    r.in_window = 0;
+                    r.window++;
+                    break;   // the rest of this router's batches belong to its next window
+                }
+            }
+        }
+        S->rr = (S->rr + 1) % std::max<uint32_t>(1, R);
+        if (group.empty() && closes.empty()) {
+            if (S->stop && S->queued == 0 && S->closing.empty()) return;
+            if (!S->closing.empty()) {
+                lk.unlock();
+                srv_reap(S, true);
+                lk.lock();
+                continue;
+            }
+            S->cv_work.wait(lk);
+            continue;
+        }
+        S->st.groups += group.empty() ? 0 : 1;
+        lk.unlock();
+        // ---- device work outside the lock
+        spd_status st = SPD_OK;
+        if (!group.empty()) st = scan_work(S->ctx, group, S->scan_s);
+        for (auto &c : closes) {
+            if (st) break;
+            hipEvent_t scanned = srv_event(S), fin = srv_event(S);
+            if (!scanned || !fin) {
+                st = SPD_E_HIP;
+                break;
+            }
+            // the close waits only for the scans issued so far; later groups overlap it
+            if (hipEventRecord(scanned, S->scan_s) != hipSuccess || hipStreamWaitEvent(S->close_s, scanned, 0) != hipSuccess) {
+                st = SPD_E_HIP;
+                break;
+            }
+            Slot &sl = S->ctx->slots[c.slot];
+            st = S->cfg.use_graphs ? close_launch_graph(S->ctx, sl, S->cbs[c.slot], S->close_s)
+                                   : close_launch(S->ctx, sl, S->cbs[c.slot], S->close_s);
+            if (st) break;
+            if (hipEventRecord(fin, S->close_s) != hipSuccess) {
+                st = SPD_E_HIP;
+                break;
+            }
+            std::lock_guard<std::mutex> g(S->mu);
+            S->ev_pool.push_back(scanned);   // reusable once recorded again later (ordering kept by the stream)
+            S->closing.push_back(SrvClosing{c.slot, c.router, c.window, c.pairs, c.t_req, fin});
+        }
+        if (st) {
+            srv_fault(S, st);
+            lk.lock();
+            return;
+        }
+        srv_reap(S, false);
+        lk.lock();
+        S->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, spd_server **out) {
+    if (!out || !p || !cfg) return SPD_E_INVALID;
+    *out = nullptr;
+    if (cfg->n_routers < 1 || cfg->n_routers > 65536) return SPD_E_INVALID;
+    if (p->window_slices) return SPD_E_INVALID;   // the serving loop runs discrete windows
+    spd_server *S = new (std::nothrow) spd_server();
+    if (!S) return SPD_E_NOMEM;
+    S->cfg = *cfg;
+    if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = 4ull << 30;
+    if (!S->cfg.max_group_pairs) S->cfg.max_group_pairs = 64ull << 20;
+    if (!S->cfg.max_group_batches) S->cfg.max_group_batches = kMaxGroup;
+    S->cfg.max_group_batches = std::min<uint32_t>(S->cfg.max_group_batches, 4096);
+    spd_status st = ctx_create(p, 0, 0, S->cfg.hbm_budget_bytes, &S->ctx);
+    if (st) {
+        delete S;
+        return st;
+    }
+    spd_ctx *ctx = S->ctx;
+    DeviceGuard dg(ctx->device);
+    // scratch for the largest fused group, reserved before the slots so admission never frees it
+    BinGeometry g{};
+    if (bin_geometry(ctx, &g)) {
+        const uint64_t tiles = S->cfg.max_group_pairs / g.tile_pairs + S->cfg.max_group_batches + 1;
+        st = ensure_scratch(ctx, tiles * g.region, tiles * (g.nb + 1), nullptr);
+        if (st) {
+            spd_server_destroy(S);
+            return st;
+        }
+    }
+    const uint64_t per_slot = ctx->slot_bytes + (uint64_t)kRecInit * 8 + 64;
+    uint64_t room = ctx->budget > ctx->held ? ctx->budget - ctx->held : 0;
+    uint32_t n_slots = (uint32_t)std::min<uint64_t>(room / per_slot, 65536);
+    if (S->cfg.max_slots) n_slots = std::min(n_slots, S->cfg.max_slots);
+    if (n_slots == 0) {
+        ctx->err = "HBM budget leaves no room for a window slot";
+        spd_server_destroy(S);
+        return SPD_E_NOMEM;
+    }
+    ctx->slots.resize(n_slots);
+    S->cbs.resize(n_slots);
+    for (uint32_t i = 0; i < n_slots; ++i) {
+        st = slot_alloc(ctx, ctx->slots[i]);
+        if (!st) st = close_buf_init(ctx, S->cbs[i]);
+        if (st) {
+            spd_server_destroy(S);
+            return st;
+        }
+        S->free_slots.push_back((int)(n_slots - 1 - i));
+    }
+    S->st.slots = n_slots;
+    S->routers.resize(S->cfg.n_routers);
+    if (hipStreamCreateWithFlags(&S->scan_s, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->close_s, hipStreamNonBlocking) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        spd_server_destroy(S);
+        return SPD_E_HIP;
+    }
+    S->worker = std::thread(srv_loop, S);
+    *out = S;
+    return SPD_OK;
+}
+
+spd_status spd_server_submit(spd_server *S, uint32_t router, const uint32_t *pairs_dev, uint64_t n_pairs, uint32_t flags) {
+    if (!S) return SPD_E_INVALID;
+    if (router >= S->cfg.n_routers) return SPD_E_STATE;
+    if (n_pairs && !pairs_dev) return SPD_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(pairs_dev) % 8) return SPD_E_INVALID;
+    if (flags & ~SPD_SUBMIT_CLOSE) return SPD_E_INVALID;
+    const Clock::time_point t = Clock::now();
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->fault) return S->fault;
+    if (S->stop) return SPD_E_STATE;
+    if (n_pairs == 0 && !(flags & SPD_SUBMIT_CLOSE)) return SPD_OK;
+    S->routers[router].q.push_back(SrvPending{pairs_dev, n_pairs, flags, t});
+    S->queued++;
+    S->st.batches++;
+    S->st.pairs += n_pairs;
+    S->cv_work.notify_one();
+    return SPD_OK;
+}
+
+spd_status spd_server_replay(spd_server *S, const spd_arrival *sched, uint64_t n, double *elapsed_s) {
+    if (!S || (n && !sched)) return SPD_E_INVALID;
+    const Clock::time_point t0 = Clock::now();
+    for (uint64_t i = 0; i < n; ++i) {
+        const auto due = t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(sched[i].t_s));
+        for (;;) {
+            const auto now = Clock::now();
+            if (now >= due) break;
+            if (due - now > std::chrono::microseconds(200)) std::this_thread::sleep_for(due - now - std::chrono::microseconds(100));
+        }
+        spd_status st = spd_server_submit(S, sched[i].router, sched[i].pairs_dev, sched[i].n_pairs, sched[i].flags);
+        if (st) return st;
+    }
+    if (elapsed_s) *elapsed_s = std::chrono::duration<double>(Clock::now() - t0).count();
+    return SPD_OK;
+}
+
+spd_status spd_server_next(spd_server *S, spd_window_result *hdr, spd_superpoint *out_host, uint32_t cap,
+                           int32_t timeout_ms) {
+    if (!S || !hdr || (cap && !out_host)) return SPD_E_INVALID;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto ready = [&] { return !S->done.empty() || S->fault; };
+    if (timeout_ms < 0) S->cv_done.wait(lk, ready);
+    else S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
+    if (S->done.empty()) return S->fault ? S->fault : SPD_E_AGAIN;
+    SrvResult r = std::move(S->done.front());
+    S->done.pop_front();
+    lk.unlock();
+    *hdr = r.hdr;
+    const uint32_t w = std::min<uint32_t>(cap, (uint32_t)r.sp.size());
+    if (w) std::memcpy(out_host, r.sp.data(), (size_t)w * sizeof(spd_superpoint));
+    return r.sp.size() > cap ? SPD_E_TRUNCATED : SPD_OK;
+}
+
+spd_status spd_server_drain(spd_server *S) {
+    if (!S) return SPD_E_INVALID;
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_work.notify_all();
+    bool stuck = false;
+    S->cv_done.wait(lk, [&] {
+        if (S->fault) return true;
+        if (!S->closing.empty()) return false;
+        if (!S->queued) return true;   // a window without a close request simply stays open
+        // every slot is held by an open window that will never close while the routers that
+        // still have batches wait for one: no progress is possible
+        bool movable = !S->free_slots.empty();
+        for (auto &r : S->routers) movable = movable || (r.slot >= 0 && !r.q.empty());
+        stuck = !movable;
+        return stuck;
+    });
+    if (S->fault) return S->fault;
+    if (stuck) {
+        S->err = "all window slots are held by open windows; queued batches cannot be admitted";
+        return SPD_E_STATE;
+    }
+    lk.unlock();
+    hipError_t e = hipStreamSynchronize(S->scan_s);
+    return e == hipSuccess ? SPD_OK : SPD_E_HIP;
+}
+
+spd_status spd_server_get_stats(spd_server *S, spd_server_stats *out) {
+    if (!S || !out) return SPD_E_INVALID;
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->st;
+    return SPD_OK;
+}
+
+spd_status spd_server_set_tuning(spd_server *S, const spd_tuning *t) {
+    if (!S || !t) return SPD_E_INVALID;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->queued || !S->closing.empty()) return SPD_E_STATE;
+    return spd_set_tuning(S->ctx, t);
+}
+
+const char *spd_server_last_error(spd_server *S) {
+    if (!S) return "";
+    std::lock_guard<std::mutex> lk(S->mu);
+    return S->err.empty() ? S->ctx->err.c_str() : S->err.c_str();
+}
+
+void spd_server_destroy(spd_server *S) {
+    if (!S) return;
+    if (S->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+        }
+        S->cv_work.notify_all();
+        S->worker.join();
+    }
+    if (S->ctx) {
+        DeviceGuard dg(S->ctx->device);
+        (void)hipDeviceSynchronize();
+        for (auto &cb : S->cbs) close_buf_free(S->ctx, cb);
+        for (auto e : S->ev_pool) (void)hipEventDestroy(e);
+        for (auto &c : S->closing) (void)hipEventDestroy(c.done);
+        if (S->scan_s) (void)hipStreamDestroy(S->scan_s);
+        if (S->close_s) (void)hipStreamDestroy(S->close_s);
+        spd_destroy(S->ctx);
+    }
+    delete S;
+}
 
 }  // extern "C"
