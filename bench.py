@@ -210,11 +210,11 @@ def main() -> int:
     dom_launches, dom_ms = kinds[dom]
     avg_ms = dom_ms / dom_launches
     # every scan kernel launch covers all n pairs of the step: 8 B of algorithmic traffic per pair
-    if dom not in ("bin", "transpose", "apply", "direct", "fill") or dom_launches != args.steps:
+    if dom not in ("bin", "transpose", "apply", "direct", "fill", "count", "offsets") or dom_launches != args.steps:
         raise RuntimeError(f"unexpected dominant kernel {dom} ({dom_launches} launches)")
     alg_bytes = BYTES_PER_PAIR * n
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    scan_kinds = ("bin", "transpose", "apply", "fill", "direct")
+    scan_kinds = ("bin", "transpose", "apply", "fill", "direct", "count", "offsets")
     scan_ms = sum(kinds.get(k, (0, 0.0))[1] for k in scan_kinds) / args.steps
     close_dev_ms = kinds.get("close", (0, 0.0))[1] / max(1, kinds.get("close", (1, 0))[0])
     traffic = measured_traffic()

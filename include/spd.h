@@ -104,6 +104,10 @@ typedef struct spd_tuning {
     uint32_t close_block;      /* end-of-window kernel: threads per workgroup */
     uint64_t launch_pairs;     /* binned scan: at most this many pairs per bin/apply launch (0: no limit);
                                   smaller launches keep their items resident in the Infinity Cache */
+    uint32_t apply_unroll;     /* binned scan: tile segments each wavefront loads at once (8, 16, 32) */
+    uint32_t bin_mode;         /* binned scan layout: 0 = per-tile regions (one pass over the pairs);
+                                  1 = bucket-major (an exact counting pass first, then contiguous
+                                  per-bucket items that the apply phase streams) */
 } spd_tuning;
 
 typedef struct spd_stats {
@@ -125,7 +129,9 @@ typedef struct spd_stats {
 #define SPD_K_MERGE 5      /* router merge */
 #define SPD_K_CLOSE 6      /* end-of-window candidate rebuild and filter */
 #define SPD_K_FILL 7       /* clears (window reset, counters) */
-#define SPD_K_KINDS 8
+#define SPD_K_COUNT 8      /* bucket-major binned scan: exact per-tile counts */
+#define SPD_K_OFFSETS 9    /* bucket-major binned scan: per-tile segment offsets */
+#define SPD_K_KINDS 10
 
 typedef struct spd_profile {
     uint64_t launches[SPD_K_KINDS];

@@ -50,7 +50,7 @@ class SpdBatch(ctypes.Structure):
 class SpdTuning(ctypes.Structure):
     _fields_ = [("direct_max_pairs", u64), ("bucket_bits", u32), ("tile_pairs", u32), ("bin_block", u32),
                 ("apply_block", u32), ("direct_block", u32), ("direct_grid_per_cu", u32), ("seav_lds", u32),
-                ("close_block", u32), ("launch_pairs", u64)]
+                ("close_block", u32), ("launch_pairs", u64), ("apply_unroll", u32), ("bin_mode", u32)]
 
 
 class SpdStats(ctypes.Structure):
@@ -58,11 +58,11 @@ class SpdStats(ctypes.Structure):
                 ("candidates_last", u64), ("reported_last", u64), ("device_bytes", u64)]
 
 
-K_KINDS = ["direct", "stamp", "bin", "transpose", "apply", "merge", "close", "fill"]
+K_KINDS = ["direct", "stamp", "bin", "transpose", "apply", "merge", "close", "fill", "count", "offsets"]
 
 
 class SpdProfile(ctypes.Structure):
-    _fields_ = [("launches", u64 * 8), ("total_ms", ctypes.c_double * 8)]
+    _fields_ = [("launches", u64 * len(K_KINDS)), ("total_ms", ctypes.c_double * len(K_KINDS))]
 
 
 class SpdServerConfig(ctypes.Structure):

@@ -13,7 +13,7 @@ from typing import Dict, List, Optional, Tuple
 
 _CACHE: Dict[tuple, dict] = {}
 
-SCAN_KINDS = ("direct", "bin", "transpose", "apply", "fill")
+SCAN_KINDS = ("direct", "bin", "transpose", "apply", "fill", "count", "offsets")
 
 
 def _scan_ms(det, x, reps: int) -> float:

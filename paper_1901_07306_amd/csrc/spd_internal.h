@@ -99,6 +99,13 @@ hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t
 hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
                       uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s);
 hipError_t launch_transpose(const uint32_t *meta, uint32_t *metaT, uint32_t rows, uint32_t cols, hipStream_t s);
+hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+                        uint32_t n_tiles, uint32_t *cnt, hipStream_t s);
+hipError_t launch_offsets(const uint32_t *cnt, uint32_t *cntT, uint32_t *offT, uint32_t *off, uint32_t *tot,
+                          uint32_t *base, const uint32_t *tile_lo, const uint32_t *tile_hi, uint32_t n_slots,
+                          uint32_t nb, uint32_t n_tiles, hipStream_t s);
+hipError_t launch_bin_bm(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+                         uint32_t n_tiles, uint32_t *items, const uint32_t *off, const SlotPtrs *slots, hipStream_t s);
 struct ApplySlot {
     uint32_t *ldca;
     uint32_t *seav_w;
@@ -107,7 +114,9 @@ struct ApplySlot {
     uint32_t pad;
 };
 hipError_t launch_apply(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
-                        const uint32_t *metaT, uint32_t n_tiles, uint32_t block, hipStream_t s);
+                        const uint32_t *metaT, uint32_t n_tiles, uint32_t block, uint32_t unroll, hipStream_t s);
+hipError_t launch_apply_bm(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
+                           const uint32_t *base, uint32_t block, hipStream_t s);
 hipError_t launch_or_merge(uint32_t *dst, const uint32_t *const *src, uint32_t n_src, uint64_t n_words, hipStream_t s);
 hipError_t launch_max_merge_u16(uint16_t *dst, const uint16_t *const *src, uint32_t n_src, uint64_t n_elems,
                                 hipStream_t s);

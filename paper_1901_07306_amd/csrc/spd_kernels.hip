@@ -213,9 +213,15 @@ __device__ void bucket_offsets(uint32_t *cl, uint32_t *cs, uint32_t nb, uint32_t
     __syncthreads();
 }
 
-template <int LR, int PPT, int BLOCK>
+// BM = false: each tile writes its items bucket-major into its own region (item j of the tile in
+//             64-bit word j / 3) plus its nb + 1 bucket offsets in meta[tile].
+// BM = true:  the tile's segment for bucket b goes to global item offset off[tile][b] (computed
+//             beforehand from exact per-tile counts), padded to a multiple of 3 items with copies
+//             of its last item, so every bucket's items are contiguous over all tiles.
+template <int LR, int PPT, int BLOCK, bool BM>
 __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTable bt, SlotTable st,
-                                               uint32_t *__restrict__ items, uint32_t *__restrict__ meta) {
+                                               uint32_t *__restrict__ items, uint32_t *__restrict__ meta,
+                                               const uint32_t *__restrict__ off) {
     extern __shared__ uint32_t lds[];
     const uint32_t nb = g.nb;
     uint32_t *cl = lds;                  // [nb + 1] LDCA counts, then offsets
@@ -279,7 +285,20 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
         }
     }
     __syncthreads();
-    const uint32_t ns = misc[0] < g.scap ? misc[0] : g.scap;
+    // a tile with more sampled pairs than it can stage records all of them directly (the decision
+    // depends only on the tile's sampled count, so a counting pass can repeat it)
+    uint32_t ns = misc[0];
+    if (ns > g.scap) {
+        uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
+        for (uint32_t e = tid; e < g.scap; e += BLOCK) {
+            const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
+            for (uint32_t r = 0; r < c.sr; ++r) {
+                uint32_t bit = seav_byte(hip, r, c) * 8u + b;
+                global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
+            }
+        }
+        ns = 0;
+    }
     for (uint32_t e = tid; e < ns; e += BLOCK) {
         const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
         for (uint32_t r = 0; r < c.sr; ++r) {
@@ -304,58 +323,335 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
         }
     }
     __syncthreads();
-    // items are at most 21 bits (S <= 20): three per 64-bit word, item j in word j / 3
-    const uint32_t total = cl[nb];
-    uint64_t *out = reinterpret_cast<uint64_t *>(items + (uint64_t)tile * g.region);
-    const uint32_t n64 = (total + 2) / 3;
-    for (uint32_t i = tid; i < n64; i += BLOCK) {
-        const uint32_t j = 3 * i;
-        uint64_t v = stage[j];
-        if (j + 1 < total) v |= (uint64_t)stage[j + 1] << 21;
-        if (j + 2 < total) v |= (uint64_t)stage[j + 2] << 42;
-        out[i] = v;
+    // items are at most 21 bits (S <= 20): three per 64-bit word
+    if (!BM) {
+        const uint32_t total = cl[nb];
+        uint64_t *out = reinterpret_cast<uint64_t *>(items + (uint64_t)tile * g.region);
+        const uint32_t n64 = (total + 2) / 3;
+        for (uint32_t i = tid; i < n64; i += BLOCK) {
+            const uint32_t j = 3 * i;
+            uint64_t v = stage[j];
+            if (j + 1 < total) v |= (uint64_t)stage[j + 1] << 21;
+            if (j + 2 < total) v |= (uint64_t)stage[j + 2] << 42;
+            out[i] = v;
+        }
+        uint32_t *mo = meta + (uint64_t)tile * (nb + 1);
+        for (uint32_t i = tid; i <= nb; i += BLOCK) mo[i] = cl[i];
+    } else {
+        // the SEAV cursors are no longer needed: reuse them for this tile's global offsets
+        const uint32_t *ot = off + (uint64_t)tile * nb;
+        for (uint32_t b = tid; b < nb; b += BLOCK) cs[b] = ot[b];
+        __syncthreads();
+        uint64_t *out = reinterpret_cast<uint64_t *>(items);
+        const uint32_t lane = tid & 63u, wid = tid / 64u;
+        for (uint32_t b = wid; b < nb; b += BLOCK / 64) {
+            const uint32_t beg = cl[b], cnt = cl[b + 1] - beg;
+            if (cnt == 0) continue;
+            const uint32_t last = stage[beg + cnt - 1];
+            const uint64_t w0 = cs[b] / 3;
+            for (uint32_t w = lane; 3 * w < cnt; w += 64) {
+                const uint32_t j = 3 * w;
+                uint64_t v = stage[beg + j];
+                v |= (uint64_t)(j + 1 < cnt ? stage[beg + j + 1] : last) << 21;
+                v |= (uint64_t)(j + 2 < cnt ? stage[beg + j + 2] : last) << 42;
+                out[w0 + w] = v;
+            }
+        }
     }
-    uint32_t *mo = meta + (uint64_t)tile * (nb + 1);
-    for (uint32_t i = tid; i <= nb; i += BLOCK) mo[i] = cl[i];
 }
 
+// Exact per-tile item counts by bucket (the first pass of the bucket-major layout): the same bit
+// addresses as k_bin, counted in LDS, SEAV items left out for tiles that record them directly.
 template <int LR, int PPT, int BLOCK>
-static void launch_bin_t(const Consts &c, const BinGeometry &g, const BatchTable &bt, const SlotTable &st,
-                         uint32_t n_tiles, uint32_t *items, uint32_t *meta, hipStream_t s) {
-    hipLaunchKernelGGL((k_bin<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st, items, meta);
+__global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchTable bt, uint32_t *__restrict__ cnt) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t nb = g.nb;
+    uint32_t *hl = lds;              // [nb] LDCA items
+    uint32_t *hs = hl + nb;          // [nb] SEAV items
+    uint32_t *misc = hs + nb;        // [0] sampled pairs
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tile = blockIdx.x;
+    uint32_t bi = 0;
+    while (bi + 1 < bt.n && bt.b[bi + 1].first_tile <= tile) ++bi;
+    const BatchDesc B = bt.b[bi];
+    const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
+    const uint32_t seav_base = (uint32_t)c.ldca_bits;
+    for (uint32_t i = tid; i < 2 * nb; i += BLOCK) hl[i] = 0;
+    if (tid == 0) misc[0] = 0;
+    const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+    u32x2 pr[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
+        pr[j] = idx < B.n ? __builtin_nontemporal_load(pairs + idx) : u32x2{0u, 0u};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (p0 + (uint64_t)j * BLOCK + tid >= B.n) continue;
+        const uint32_t hip = pr[j].x, oip = pr[j].y;
+        const uint32_t q = ldc_bit(oip, c);
+#pragma unroll
+        for (int r = 0; r < LR; ++r) {
+            uint32_t bit = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
+            atomicAdd(&hl[bit >> g.S], 1u);
+        }
+        if (sampled(oip, c)) {
+            atomicAdd(&misc[0], 1u);
+            const uint32_t b = se_bit(oip, c);
+            for (uint32_t r = 0; r < c.sr; ++r) {
+                uint32_t bit = seav_base + seav_byte(hip, r, c) * 8u + b;
+                atomicAdd(&hs[bit >> g.S], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    const bool direct = misc[0] > g.scap;
+    uint32_t *co = cnt + (uint64_t)tile * nb;
+    for (uint32_t b = tid; b < nb; b += BLOCK) co[b] = hl[b] + (direct ? 0u : hs[b]);
+}
+
+// kind: 0 = k_bin (tile regions), 1 = k_bin (bucket-major), 2 = k_count
+template <int LR, int PPT, int BLOCK>
+static void launch_bin_t(int kind, const Consts &c, const BinGeometry &g, const BatchTable &bt, const SlotTable &st,
+                         uint32_t n_tiles, uint32_t *items, uint32_t *meta, const uint32_t *off, hipStream_t s) {
+    if (kind == 0)
+        hipLaunchKernelGGL((k_bin<LR, PPT, BLOCK, false>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st, items,
+                           meta, off);
+    else if (kind == 1)
+        hipLaunchKernelGGL((k_bin<LR, PPT, BLOCK, true>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st, items,
+                           meta, off);
+    else
+        hipLaunchKernelGGL((k_count<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), (2 * g.nb + 1) * 4u, s, c, g, bt, meta);
 }
 
 template <int LR>
-static hipError_t launch_bin_lr(const Consts &c, const BinGeometry &g, const BatchTable &bt, const SlotTable &st,
-                                uint32_t n_tiles, uint32_t *items, uint32_t *meta, hipStream_t s) {
+static hipError_t launch_bin_lr(int kind, const Consts &c, const BinGeometry &g, const BatchTable &bt,
+                                const SlotTable &st, uint32_t n_tiles, uint32_t *items, uint32_t *meta,
+                                const uint32_t *off, hipStream_t s) {
     const uint32_t ppt = g.tile_pairs / g.block;
-    if (g.block == 1024 && ppt == 16) launch_bin_t<LR, 16, 1024>(c, g, bt, st, n_tiles, items, meta, s);
-    else if (g.block == 1024 && ppt == 8) launch_bin_t<LR, 8, 1024>(c, g, bt, st, n_tiles, items, meta, s);
-    else if (g.block == 1024 && ppt == 4) launch_bin_t<LR, 4, 1024>(c, g, bt, st, n_tiles, items, meta, s);
-    else if (g.block == 512 && ppt == 16) launch_bin_t<LR, 16, 512>(c, g, bt, st, n_tiles, items, meta, s);
-    else if (g.block == 512 && ppt == 8) launch_bin_t<LR, 8, 512>(c, g, bt, st, n_tiles, items, meta, s);
-    else if (g.block == 512 && ppt == 4) launch_bin_t<LR, 4, 512>(c, g, bt, st, n_tiles, items, meta, s);
-    else if (g.block == 256 && ppt == 16) launch_bin_t<LR, 16, 256>(c, g, bt, st, n_tiles, items, meta, s);
-    else if (g.block == 256 && ppt == 8) launch_bin_t<LR, 8, 256>(c, g, bt, st, n_tiles, items, meta, s);
+#define SPD_BIN_CASE(B, P) \
+    else if (g.block == B && ppt == P) launch_bin_t<LR, P, B>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
+    if (false) {
+    }
+    SPD_BIN_CASE(1024, 16) SPD_BIN_CASE(1024, 8) SPD_BIN_CASE(1024, 4) SPD_BIN_CASE(512, 16) SPD_BIN_CASE(512, 8)
+    SPD_BIN_CASE(512, 4) SPD_BIN_CASE(256, 16) SPD_BIN_CASE(256, 8)
+#undef SPD_BIN_CASE
     else return hipErrorInvalidConfiguration;
     return hipGetLastError();
 }
 
-hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
-                      uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s) {
+static hipError_t launch_bin_kind(int kind, const Consts &c, const BinGeometry &g, const BatchDesc *batches,
+                                  uint32_t n_batches, uint32_t n_tiles, uint32_t *items, uint32_t *meta,
+                                  const uint32_t *off, const SlotPtrs *slots, hipStream_t s) {
     BatchTable bt{};
     SlotTable st{};
     if (n_batches == 0 || n_batches > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
     for (uint32_t i = 0; i < n_batches; ++i) bt.b[i] = batches[i];
     bt.n = n_batches;
-    for (int i = 0; i < kMaxGroup; ++i) st.s[i] = slots[i];
+    if (slots)
+        for (int i = 0; i < kMaxGroup; ++i) st.s[i] = slots[i];
     switch (c.lr) {
-    case 1: return launch_bin_lr<1>(c, g, bt, st, n_tiles, items, meta, s);
-    case 2: return launch_bin_lr<2>(c, g, bt, st, n_tiles, items, meta, s);
-    case 3: return launch_bin_lr<3>(c, g, bt, st, n_tiles, items, meta, s);
-    case 4: return launch_bin_lr<4>(c, g, bt, st, n_tiles, items, meta, s);
+    case 1: return launch_bin_lr<1>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
+    case 2: return launch_bin_lr<2>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
+    case 3: return launch_bin_lr<3>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
+    case 4: return launch_bin_lr<4>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+                      uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s) {
+    return launch_bin_kind(0, c, g, batches, n_batches, n_tiles, items, meta, nullptr, slots, s);
+}
+
+hipError_t launch_bin_bm(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+                         uint32_t n_tiles, uint32_t *items, const uint32_t *off, const SlotPtrs *slots, hipStream_t s) {
+    return launch_bin_kind(1, c, g, batches, n_batches, n_tiles, items, nullptr, off, slots, s);
+}
+
+hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+                        uint32_t n_tiles, uint32_t *cnt, hipStream_t s) {
+    return launch_bin_kind(2, c, g, batches, n_batches, n_tiles, nullptr, cnt, nullptr, nullptr, s);
+}
+
+// ---- offsets of the bucket-major layout
+struct RangeTable {
+    uint32_t lo[kMaxGroup], hi[kMaxGroup];   // tile range of each slot of the launch
+    uint32_t n;
+};
+
+// One workgroup per (slot, bucket): exclusive prefix over the slot's tiles of the bucket's counts,
+// each rounded up to a multiple of 3 (whole 64-bit words).  offT[b][t] relative to the segment
+// start; tot[slot * nb + b] = the bucket's padded total.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_rowscan(const uint32_t *__restrict__ cntT, uint32_t *__restrict__ offT,
+                                                   uint32_t *__restrict__ tot, RangeTable rt, uint32_t nb,
+                                                   uint32_t n_tiles) {
+    __shared__ uint32_t wsum[BLOCK / 64 + 1];
+    const uint32_t si = blockIdx.x / nb, b = blockIdx.x % nb;
+    const uint32_t lo = rt.lo[si], hi = rt.hi[si];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+    const uint32_t *row = cntT + (uint64_t)b * n_tiles;
+    uint32_t *orow = offT + (uint64_t)b * n_tiles;
+    uint32_t carry = 0;
+    for (uint32_t t0 = lo; t0 < hi; t0 += BLOCK) {
+        const uint32_t t = t0 + tid;
+        const uint32_t v = t < hi ? (row[t] + 2) / 3 * 3 : 0u;
+        uint32_t incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t x = __shfl_up(incl, o, 64);
+            if ((int)lane >= o) incl += x;
+        }
+        if (lane == 63u) wsum[wid] = incl;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t run = 0;
+            for (uint32_t w = 0; w < BLOCK / 64; ++w) {
+                uint32_t x = wsum[w];
+                wsum[w] = run;
+                run += x;
+            }
+            wsum[BLOCK / 64] = run;
+        }
+        __syncthreads();
+        if (t < hi) orow[t] = carry + wsum[wid] + incl - v;
+        carry += wsum[BLOCK / 64];
+        __syncthreads();
+    }
+    if (tid == 0) tot[blockIdx.x] = carry;
+}
+
+// Exclusive prefix of the padded bucket totals: base[g], base[n] = all items.
+__global__ __launch_bounds__(1024) void k_basescan(const uint32_t *__restrict__ tot, uint32_t *__restrict__ base,
+                                                   uint32_t n) {
+    __shared__ uint32_t wsum[17];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+    uint32_t carry = 0;
+    for (uint32_t i0 = 0; i0 < n; i0 += 1024) {
+        const uint32_t i = i0 + tid;
+        const uint32_t v = i < n ? tot[i] : 0u;
+        uint32_t incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t x = __shfl_up(incl, o, 64);
+            if ((int)lane >= o) incl += x;
+        }
+        if (lane == 63u) wsum[wid] = incl;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t run = 0;
+            for (uint32_t w = 0; w < 16; ++w) {
+                uint32_t x = wsum[w];
+                wsum[w] = run;
+                run += x;
+            }
+            wsum[16] = run;
+        }
+        __syncthreads();
+        if (i < n) base[i] = carry + wsum[wid] + incl - v;
+        carry += wsum[16];
+        __syncthreads();
+    }
+    if (tid == 0) base[n] = carry;
+}
+
+// off[t][b] = base[slot(t) * nb + b] + offT[b][t]
+__global__ __launch_bounds__(256) void k_offsets(const uint32_t *__restrict__ offT, const uint32_t *__restrict__ base,
+                                                 uint32_t *__restrict__ off, RangeTable rt, uint32_t nb,
+                                                 uint32_t n_tiles) {
+    __shared__ uint32_t t[32][33];
+    const uint32_t bx = blockIdx.y * 32, by = blockIdx.x * 32;   // bx: bucket block, by: tile block
+    const uint32_t tx = threadIdx.x & 31u, ty = threadIdx.x >> 5;
+    for (uint32_t k = ty; k < 32; k += 8) {
+        uint32_t b = bx + k, tile = by + tx;
+        if (b < nb && tile < n_tiles) t[k][tx] = offT[(uint64_t)b * n_tiles + tile];
+    }
+    __syncthreads();
+    for (uint32_t k = ty; k < 32; k += 8) {
+        uint32_t tile = by + k, b = bx + tx;
+        if (b < nb && tile < n_tiles) {
+            uint32_t si = 0;
+            while (si + 1 < rt.n && rt.lo[si + 1] <= tile) ++si;
+            off[(uint64_t)tile * nb + b] = base[si * nb + b] + t[tx][k];
+        }
+    }
+}
+
+hipError_t launch_offsets(const uint32_t *cnt, uint32_t *cntT, uint32_t *offT, uint32_t *off, uint32_t *tot,
+                          uint32_t *base, const uint32_t *tile_lo, const uint32_t *tile_hi, uint32_t n_slots,
+                          uint32_t nb, uint32_t n_tiles, hipStream_t s) {
+    RangeTable rt{};
+    if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup || (nb + 31) / 32 > 65535u) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_slots; ++i) {
+        rt.lo[i] = tile_lo[i];
+        rt.hi[i] = tile_hi[i];
+    }
+    rt.n = n_slots;
+    hipError_t e = launch_transpose(cnt, cntT, n_tiles, nb, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rowscan<256>, dim3(n_slots * nb), dim3(256), 0, s, cntT, offT, tot, rt, nb, n_tiles);
+    hipLaunchKernelGGL(k_basescan, dim3(1), dim3(1024), 0, s, tot, base, n_slots * nb);
+    dim3 grid((n_tiles + 31) / 32, (nb + 31) / 32);
+    hipLaunchKernelGGL(k_offsets, grid, dim3(256), 0, s, offT, base, off, rt, nb, n_tiles);
+    return hipGetLastError();
+}
+
+// Phase 2 of the bucket-major layout: one workgroup per (slot, bucket) streams the bucket's
+// contiguous items (three per 64-bit word) into an LDS bitmap and writes the bucket back.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_apply_bm(BinGeometry g, ApplyTable at, const uint64_t *__restrict__ items,
+                                                    const uint32_t *__restrict__ base) {
+    extern __shared__ uint32_t bm[];
+    constexpr uint32_t U = 4;
+    const uint32_t words = 1u << (g.S - 5);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t si = blockIdx.x / g.nb, b = blockIdx.x % g.nb;
+    const ApplySlot A = at.s[si];
+    uint32_t *dst = b < g.nb_ldca ? A.ldca + (uint64_t)b * words : A.seav_w + (uint64_t)(b - g.nb_ldca) * words;
+    if (A.fresh && b < g.nb_ldca) {
+        for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = 0;
+    } else {
+        for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = dst[w];
+    }
+    __syncthreads();
+    const uint32_t w0 = base[blockIdx.x] / 3, w1 = base[blockIdx.x + 1] / 3;
+    for (uint32_t w = w0 + tid; w < w1; w += BLOCK * U) {
+        uint64_t v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) v[u] = w + u * BLOCK < w1 ? __builtin_nontemporal_load(items + w + u * BLOCK) : 0ull;
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            if (w + u * BLOCK >= w1) continue;
+#pragma unroll
+            for (uint32_t f = 0; f < 3; ++f) {
+                const uint32_t it = (uint32_t)(v[u] >> (21 * f)) & 0x1FFFFFu;
+                atomicOr(&bm[it >> 5], 1u << (it & 31u));
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t words4 = words / 4;
+    if (words4) {
+        for (uint32_t w = tid; w < words4; w += BLOCK)
+            reinterpret_cast<u32x4 *>(dst)[w] = reinterpret_cast<const u32x4 *>(bm)[w];
+    } else {
+        for (uint32_t w = tid; w < words; w += BLOCK) dst[w] = bm[w];
+    }
+}
+
+hipError_t launch_apply_bm(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
+                           const uint32_t *base, uint32_t block, hipStream_t s) {
+    ApplyTable at{};
+    if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
+    const uint32_t lds = (1u << (g.S - 5)) * 4u;
+    const uint64_t *it = reinterpret_cast<const uint64_t *>(items);
+    dim3 grid(n_slots * g.nb);
+    if (block == 1024) hipLaunchKernelGGL(k_apply_bm<1024>, grid, dim3(1024), lds, s, g, at, it, base);
+    else if (block == 512) hipLaunchKernelGGL(k_apply_bm<512>, grid, dim3(512), lds, s, g, at, it, base);
+    else if (block == 256) hipLaunchKernelGGL(k_apply_bm<256>, grid, dim3(256), lds, s, g, at, it, base);
+    else return hipErrorInvalidConfiguration;
+    return hipGetLastError();
 }
 
 // meta[rows][cols] -> metaT[cols][rows]
@@ -384,12 +680,12 @@ hipError_t launch_transpose(const uint32_t *meta, uint32_t *metaT, uint32_t rows
 
 constexpr uint32_t kApplyChunk = 1024;
 
-template <int BLOCK>
+template <int BLOCK, int U>
 __global__ __launch_bounds__(BLOCK) void k_apply(BinGeometry g, ApplyTable at, const uint32_t *__restrict__ items,
                                                  const uint32_t *__restrict__ metaT, uint32_t n_tiles) {
+    // U: tiles per wavefront per step, i.e. U segment loads in flight per lane
     extern __shared__ uint32_t lds[];
     constexpr uint32_t NW = BLOCK / 64;
-    constexpr uint32_t U = 8;   // tiles per wavefront per step: U segment loads in flight per lane
     const uint32_t words = 1u << (g.S - 5);
     uint32_t *bm = lds;
     uint32_t *mbeg = bm + words;
@@ -458,18 +754,29 @@ __global__ __launch_bounds__(BLOCK) void k_apply(BinGeometry g, ApplyTable at, c
     }
 }
 
+template <int U>
+static hipError_t launch_apply_u(const BinGeometry &g, const ApplyTable &at, uint32_t n_slots, const uint32_t *items,
+                                 const uint32_t *metaT, uint32_t n_tiles, uint32_t block, hipStream_t s) {
+    uint32_t lds = ((1u << (g.S - 5)) + 2 * kApplyChunk) * 4u;
+    dim3 grid(n_slots * g.nb);
+    if (block == 1024) hipLaunchKernelGGL((k_apply<1024, U>), grid, dim3(1024), lds, s, g, at, items, metaT, n_tiles);
+    else if (block == 512) hipLaunchKernelGGL((k_apply<512, U>), grid, dim3(512), lds, s, g, at, items, metaT, n_tiles);
+    else if (block == 256) hipLaunchKernelGGL((k_apply<256, U>), grid, dim3(256), lds, s, g, at, items, metaT, n_tiles);
+    else return hipErrorInvalidConfiguration;
+    return hipGetLastError();
+}
+
 hipError_t launch_apply(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
-                        const uint32_t *metaT, uint32_t n_tiles, uint32_t block, hipStream_t s) {
+                        const uint32_t *metaT, uint32_t n_tiles, uint32_t block, uint32_t unroll, hipStream_t s) {
     ApplyTable at{};
     if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
     for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
-    uint32_t lds = ((1u << (g.S - 5)) + 2 * kApplyChunk) * 4u;
-    dim3 grid(n_slots * g.nb);
-    if (block == 1024) hipLaunchKernelGGL(k_apply<1024>, grid, dim3(1024), lds, s, g, at, items, metaT, n_tiles);
-    else if (block == 512) hipLaunchKernelGGL(k_apply<512>, grid, dim3(512), lds, s, g, at, items, metaT, n_tiles);
-    else if (block == 256) hipLaunchKernelGGL(k_apply<256>, grid, dim3(256), lds, s, g, at, items, metaT, n_tiles);
-    else return hipErrorInvalidConfiguration;
-    return hipGetLastError();
+    switch (unroll) {
+    case 8: return launch_apply_u<8>(g, at, n_slots, items, metaT, n_tiles, block, s);
+    case 16: return launch_apply_u<16>(g, at, n_slots, items, metaT, n_tiles, block, s);
+    case 32: return launch_apply_u<32>(g, at, n_slots, items, metaT, n_tiles, block, s);
+    default: return hipErrorInvalidConfiguration;
+    }
 }
 
 // ------------------------------------------------------------------------------ merge

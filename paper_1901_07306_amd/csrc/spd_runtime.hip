@@ -72,6 +72,8 @@ struct spd_ctx {
     uint32_t *meta = nullptr;
     uint32_t *metaT = nullptr;
     uint64_t meta_words = 0;
+    uint32_t *aux = nullptr;         // bucket-major layout: padded bucket totals and their prefix
+    uint64_t aux_words = 0;
     CloseBuf cbuf;                  // end-of-window buffers of spd_close_window
     uint32_t *view = nullptr;       // sliding export: bit view words
     uint64_t view_words = 0;
@@ -205,6 +207,8 @@ void default_tuning(spd_tuning *t) {
     t->seav_lds = 0;
     t->close_block = 256;
     t->launch_pairs = 0;
+    t->apply_unroll = 8;
+    t->bin_mode = 0;
 }
 
 void order_stream(spd_ctx *ctx, hipStream_t s) {
@@ -364,6 +368,17 @@ bool bin_geometry(const spd_ctx *ctx, BinGeometry *g) {
     return false;
 }
 
+spd_status ensure_aux(spd_ctx *ctx, uint64_t words, hipStream_t s) {
+    if (words <= ctx->aux_words) return SPD_OK;
+    SPD_HIP(ctx, hipStreamSynchronize(s));
+    dev_free(ctx, &ctx->aux, ctx->aux_words * 4);
+    ctx->aux_words = 0;
+    spd_status st = dev_alloc(ctx, &ctx->aux, words * 4);
+    if (st) return st;
+    ctx->aux_words = words;
+    return SPD_OK;
+}
+
 spd_status ensure_scratch(spd_ctx *ctx, uint64_t items_words, uint64_t meta_words, hipStream_t s) {
     if (items_words > ctx->items_words || meta_words > ctx->meta_words) SPD_HIP(ctx, hipStreamSynchronize(s));
     if (items_words > ctx->items_words) {
@@ -488,19 +503,52 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
         }
         i0 = i;
         if (nbd == 0) continue;
-        spd_status st = ensure_scratch(ctx, (uint64_t)tiles * g.region, (uint64_t)tiles * (g.nb + 1), s);
-        if (st) return st;
-        {
-            ProfScope ps(ctx, SPD_K_BIN, s);
-            SPD_HIP(ctx, launch_bin(ctx->c, g, bd, nbd, tiles, ctx->items, ctx->meta, sp, s));
-        }
-        {
-            ProfScope ps(ctx, SPD_K_TRANSPOSE, s);
-            SPD_HIP(ctx, launch_transpose(ctx->meta, ctx->metaT, tiles, g.nb + 1, s));
-        }
-        {
-            ProfScope ps(ctx, SPD_K_APPLY, s);
-            SPD_HIP(ctx, launch_apply(g, as, nsl, ctx->items, ctx->metaT, tiles, ctx->tune.apply_block, s));
+        if (ctx->tune.bin_mode == 0) {
+            spd_status st = ensure_scratch(ctx, (uint64_t)tiles * g.region, (uint64_t)tiles * (g.nb + 1), s);
+            if (st) return st;
+            {
+                ProfScope ps(ctx, SPD_K_BIN, s);
+                SPD_HIP(ctx, launch_bin(ctx->c, g, bd, nbd, tiles, ctx->items, ctx->meta, sp, s));
+            }
+            {
+                ProfScope ps(ctx, SPD_K_TRANSPOSE, s);
+                SPD_HIP(ctx, launch_transpose(ctx->meta, ctx->metaT, tiles, g.nb + 1, s));
+            }
+            {
+                ProfScope ps(ctx, SPD_K_APPLY, s);
+                SPD_HIP(ctx, launch_apply(g, as, nsl, ctx->items, ctx->metaT, tiles, ctx->tune.apply_block,
+                                          ctx->tune.apply_unroll, s));
+            }
+        } else {
+            // bucket-major: padded items per tile <= its items + 2 per bucket; 3 items per 64 bits
+            const uint64_t max_items = (uint64_t)tiles * (g.cap + 2ull * g.nb);
+            if (max_items >= (1ull << 32)) return fail(ctx, SPD_E_INVALID, "launch too large for 32-bit item offsets");
+            spd_status st = ensure_scratch(ctx, (max_items + 2) / 3 * 2 + 4, (uint64_t)tiles * (g.nb + 1), s);
+            if (!st) st = ensure_aux(ctx, 2ull * nsl * g.nb + 2, s);
+            if (st) return st;
+            uint32_t lo[kMaxGroup], hi[kMaxGroup];
+            for (uint32_t k = 0; k < nsl; ++k) {
+                lo[k] = as[k].tile_lo;
+                hi[k] = as[k].tile_hi;
+            }
+            uint32_t *tot = ctx->aux, *base = ctx->aux + nsl * g.nb;
+            {
+                ProfScope ps(ctx, SPD_K_COUNT, s);
+                SPD_HIP(ctx, launch_count(ctx->c, g, bd, nbd, tiles, ctx->meta, s));
+            }
+            {
+                ProfScope ps(ctx, SPD_K_OFFSETS, s);
+                SPD_HIP(ctx, launch_offsets(ctx->meta, ctx->metaT, ctx->meta, ctx->metaT, tot, base, lo, hi, nsl, g.nb,
+                                            tiles, s));
+            }
+            {
+                ProfScope ps(ctx, SPD_K_BIN, s);
+                SPD_HIP(ctx, launch_bin_bm(ctx->c, g, bd, nbd, tiles, ctx->items, ctx->metaT, sp, s));
+            }
+            {
+                ProfScope ps(ctx, SPD_K_APPLY, s);
+                SPD_HIP(ctx, launch_apply_bm(g, as, nsl, ctx->items, base, ctx->tune.apply_block, s));
+            }
         }
         // later groups of the same call OR into these slots
         for (uint32_t k = 0; k < nsl; ++k)
@@ -808,6 +856,7 @@ void spd_destroy(spd_ctx *ctx) {
         dev_free(ctx, &ctx->items, ctx->items_words * 4);
         dev_free(ctx, &ctx->meta, ctx->meta_words * 4);
         dev_free(ctx, &ctx->metaT, ctx->meta_words * 4);
+        dev_free(ctx, &ctx->aux, ctx->aux_words * 4);
         close_buf_free(ctx, ctx->cbuf);
         dev_free(ctx, &ctx->view, ctx->view_words * 4);
         if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
@@ -1027,6 +1076,8 @@ spd_status spd_set_tuning(spd_ctx *ctx, const spd_tuning *t) {
         return fail(ctx, SPD_E_INVALID, "direct_block");
     if (t->direct_grid_per_cu < 1 || t->direct_grid_per_cu > 64) return fail(ctx, SPD_E_INVALID, "direct_grid_per_cu");
     if (t->close_block != 64 && t->close_block != 128 && t->close_block != 256) return fail(ctx, SPD_E_INVALID, "close_block");
+    if (t->apply_unroll != 8 && t->apply_unroll != 16 && t->apply_unroll != 32) return fail(ctx, SPD_E_INVALID, "apply_unroll");
+    if (t->bin_mode > 1) return fail(ctx, SPD_E_INVALID, "bin_mode");
     ctx->tune = *t;
     BinGeometry g{};
     if (t->direct_max_pairs < UINT64_MAX && !bin_geometry(ctx, &g)) {

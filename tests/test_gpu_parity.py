@@ -26,6 +26,10 @@ import paper_1901_07306_amd as spd  # noqa: E402
 DIRECT = dict(direct_max_pairs=1 << 62)
 BINNED_SMALL = dict(direct_max_pairs=0, tile_pairs=2048, bucket_bits=12, bin_block=512, apply_block=256)
 BINNED_DEFAULT = dict(direct_max_pairs=0)
+BINNED_CHUNKED = dict(direct_max_pairs=0, launch_pairs=50_000, tile_pairs=8192)
+BUCKET_MAJOR = dict(direct_max_pairs=0, bin_mode=1)
+BUCKET_MAJOR_SMALL = dict(direct_max_pairs=0, bin_mode=1, tile_pairs=2048, bucket_bits=12, bin_block=512,
+                          apply_block=256, launch_pairs=70_000)
 
 
 def detector(mp, n_routers=1, isb=None, ibn=None, **tune):
@@ -45,11 +49,15 @@ PARAMS = {
 
 
 @pytest.mark.parametrize("pname", list(PARAMS))
-@pytest.mark.parametrize("mode", ["direct", "binned_small", "binned_default"])
+MODES = {"direct": DIRECT, "binned_small": BINNED_SMALL, "binned_default": BINNED_DEFAULT,
+         "binned_chunked": BINNED_CHUNKED, "bucket_major": BUCKET_MAJOR, "bucket_major_small": BUCKET_MAJOR_SMALL}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
 def test_scan_and_close_parity(pname, mode):
     mp = PARAMS[pname]
     log(f"case params={pname} mode={mode}")
-    tune = {"direct": DIRECT, "binned_small": BINNED_SMALL, "binned_default": BINNED_DEFAULT}[mode]
+    tune = MODES[mode]
     rng = np.random.default_rng(hash((pname, mode)) % (1 << 32))
     heavy, _ = heavy_hosts(rng, 8, 3000, noise=150_001)   # ragged: not a multiple of any tile
     det = detector(mp, **tune)
@@ -109,11 +117,11 @@ def test_oip_whose_h1_is_zero_is_sampled():
             det.close()
 
 
-@pytest.mark.parametrize("mode", ["direct", "binned_small"])
+@pytest.mark.parametrize("mode", ["direct", "binned_small", "bucket_major_small"])
 def test_routers_fused_batches_and_merge(mode):
     mp = PARAMS["tiny_r20_sr3"].replace(theta=512)
     log(f"case routers mode={mode}")
-    tune = DIRECT if mode == "direct" else BINNED_SMALL
+    tune = MODES[mode]
     rng = np.random.default_rng(5)
     R = 5
     det = detector(mp, n_routers=R, **tune)
@@ -312,6 +320,23 @@ def test_plain_64m_full_window():
         det.close()
 
 
+def test_bucket_major_overflow_tile_records_seav_directly():
+    """A tile whose sampled pairs exceed its LDS reservation records its SEAV bits directly; the
+    counting pass must leave them out consistently (bucket-major layout)."""
+    mp = st.CONFIGS["plain_64m"].params.replace(theta=8)    # tau = 0: every pair is sampled
+    rng = np.random.default_rng(71)
+    pairs, _ = heavy_hosts(rng, 40, 1200, noise=30_000)
+    for tune in (BUCKET_MAJOR, BUCKET_MAJOR_SMALL, BINNED_DEFAULT):
+        det = detector(mp, **tune)
+        try:
+            det.scan(0, to_dev(pairs))
+            ref = oracle_sketch(mp, pairs)
+            assert_same_sketch(det, 0, ref, f"overflow {tune}")
+            assert_same_report(det.close_window(0, cap=1 << 18), ref.detect(), "overflow report")
+        finally:
+            det.close()
+
+
 def test_many_batches_one_call_binned():
     """More batches in one fused call than one launch takes: the call is split into launch groups
     and later groups must OR into the slots the earlier ones wrote."""
@@ -321,11 +346,12 @@ def test_many_batches_one_call_binned():
     cuts = np.sort(rng.choice(np.arange(1, len(pairs)), size=70, replace=False))
     parts = np.split(pairs, cuts)
     owner = [0 if i % 3 else 1 for i in range(len(parts))]
-    det = detector(mp, n_routers=2, **BINNED_SMALL)
-    try:
-        det.scan_batches([(o, to_dev(p)) for o, p in zip(owner, parts)])
-        for r in range(2):
-            mine = np.concatenate([p for o, p in zip(owner, parts) if o == r])
-            assert_same_sketch(det, r, oracle_sketch(mp, mine), f"router {r}")
-    finally:
-        det.close()
+    for tune in (BINNED_SMALL, BUCKET_MAJOR_SMALL):
+        det = detector(mp, n_routers=2, **tune)
+        try:
+            det.scan_batches([(o, to_dev(p)) for o, p in zip(owner, parts)])
+            for r in range(2):
+                mine = np.concatenate([p for o, p in zip(owner, parts) if o == r])
+                assert_same_sketch(det, r, oracle_sketch(mp, mine), f"router {r}")
+        finally:
+            det.close()

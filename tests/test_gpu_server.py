@@ -97,22 +97,23 @@ def test_serving_windows_match_oracle_and_alone():
 
 
 def test_serving_slots_follow_hbm_budget():
-    """Window slots are admitted by the HBM budget: a budget for about 3 slots gives 3."""
+    """Window slots are admitted by the HBM budget: two more slots' worth of budget gives exactly
+    two more slots."""
     det = spd.Detector(spd.params_from(MP))
     d = det.derived
     det.close()
-    slot = (d.ldca_words * 4 + 255) // 256 * 256 + (1 << 17) + 65536 * 8 + 64
-    base = spd.Server(spd.params_from(MP), n_routers=2, hbm_budget_bytes=1 << 30, max_group_pairs=1 << 20)
-    held_before = base.stats["slots"]
-    base.close()
-    assert held_before > 3
-    # scratch for 1 Mi-pair groups is small; leave room for 3.5 slots beyond 16 MiB of it
-    srv = spd.Server(spd.params_from(MP), n_routers=2, hbm_budget_bytes=(16 << 20) + int(3.5 * slot),
-                     max_group_pairs=1 << 20)
-    try:
-        assert 1 <= srv.stats["slots"] <= 4
-    finally:
-        srv.close()
+    # per slot: LDCA (256-byte aligned) + SEAV padded to 128 KiB + its record buffer + counters
+    per_slot = (d.ldca_words * 4 + 255) // 256 * 256 + (-(-d.seav_bytes // (1 << 17)) << 17) + 65536 * 8 + 64
+    budget = 64 << 20
+    counts = []
+    for extra in (0, 2):
+        srv = spd.Server(spd.params_from(MP), n_routers=2, hbm_budget_bytes=budget + extra * per_slot,
+                         max_group_pairs=1 << 20)
+        try:
+            counts.append(srv.stats["slots"])
+        finally:
+            srv.close()
+    assert counts[0] >= 1 and counts[1] == counts[0] + 2, counts
 
 
 def test_serving_close_flag_and_repeated_graph_replays():
