@@ -48,11 +48,11 @@ PARAMS = {
 }
 
 
-@pytest.mark.parametrize("pname", list(PARAMS))
 MODES = {"direct": DIRECT, "binned_small": BINNED_SMALL, "binned_default": BINNED_DEFAULT,
          "binned_chunked": BINNED_CHUNKED, "bucket_major": BUCKET_MAJOR, "bucket_major_small": BUCKET_MAJOR_SMALL}
 
 
+@pytest.mark.parametrize("pname", list(PARAMS))
 @pytest.mark.parametrize("mode", list(MODES))
 def test_scan_and_close_parity(pname, mode):
     mp = PARAMS[pname]
