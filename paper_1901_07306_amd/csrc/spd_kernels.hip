@@ -242,15 +242,15 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
     for (uint32_t i = tid; i < 2 * (nb + 1); i += BLOCK) cl[i] = 0;
     if (tid == 0) misc[0] = 0;
 
+    // every lane loads unconditionally (past-the-end lanes re-read the last pair and are masked
+    // out below), so all PPT loads of a lane are in flight together
     const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+    const uint64_t last = B.n - 1;
     u32x2 pr[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
-        if (idx < B.n)
-            pr[j] = __builtin_nontemporal_load(pairs + idx);
-        else
-            pr[j] = u32x2{0u, 0u};
+        const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
+        pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
     }
     __syncthreads();
 
@@ -379,11 +379,12 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchT
     for (uint32_t i = tid; i < 2 * nb; i += BLOCK) hl[i] = 0;
     if (tid == 0) misc[0] = 0;
     const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+    const uint64_t last = B.n - 1;
     u32x2 pr[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
-        pr[j] = idx < B.n ? __builtin_nontemporal_load(pairs + idx) : u32x2{0u, 0u};
+        const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
+        pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
     }
     __syncthreads();
 #pragma unroll
@@ -618,7 +619,10 @@ __global__ __launch_bounds__(BLOCK) void k_apply_bm(BinGeometry g, ApplyTable at
     for (uint32_t w = w0 + tid; w < w1; w += BLOCK * U) {
         uint64_t v[U];
 #pragma unroll
-        for (uint32_t u = 0; u < U; ++u) v[u] = w + u * BLOCK < w1 ? __builtin_nontemporal_load(items + w + u * BLOCK) : 0ull;
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t ww = w + u * BLOCK < w1 ? w + u * BLOCK : w1 - 1;   // unconditional loads
+            v[u] = __builtin_nontemporal_load(items + ww);
+        }
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {
             if (w + u * BLOCK >= w1) continue;
@@ -714,20 +718,21 @@ __global__ __launch_bounds__(BLOCK) void k_apply(BinGeometry g, ApplyTable at, c
         for (uint32_t k0 = wid * U; k0 < nt; k0 += NW * U) {
             uint32_t v[U];
             bool ok[U];
+            // unconditional loads (lanes without an item re-read the tile's first word and are
+            // masked out), so all U loads of a lane are in flight together
+            uint64_t w[U];
+            uint32_t f[U];
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
-                const uint32_t k = k0 + u;
-                ok[u] = false;
-                v[u] = 0;
-                if (k < nt) {
-                    const uint32_t j = mbeg[k] + lane;
-                    if (j < mend[k]) {
-                        const uint64_t w = items64[(uint64_t)(t0 + k) * region64 + j / 3];
-                        v[u] = (uint32_t)(w >> (21 * (j % 3))) & 0x1FFFFFu;
-                        ok[u] = true;
-                    }
-                }
+                const uint32_t k = k0 + u < nt ? k0 + u : nt - 1;
+                const uint32_t j = mbeg[k] + lane;
+                ok[u] = (k0 + u < nt) && (j < mend[k]);
+                const uint32_t jj = ok[u] ? j : 0u;
+                f[u] = jj % 3;
+                w[u] = items64[(uint64_t)(t0 + k) * region64 + jj / 3];
             }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) v[u] = (uint32_t)(w[u] >> (21 * f[u])) & 0x1FFFFFu;
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u)
                 if (ok[u]) atomicOr(&bm[v[u] >> 5], 1u << (v[u] & 31u));
