@@ -20,6 +20,8 @@ struct Consts {
     uint32_t r, L, sr, lr;          // L = 32 - r bits of LP
     uint32_t rmask;                 // 2^r - 1
     uint32_t log2k, log2lc;
+    uint32_t sh_k, sh_lc;           // (32 - output bits) mod 32 of H3 and of LH_i; a zero-bit LH_i
+                                    // is given zero parameters, so its 32-bit value is already 0
     uint32_t isb[kMaxRows];
     uint32_t ibn[kMaxRows];
     uint32_t row_off[kMaxRows];     // byte offset of each row inside one SEA
@@ -36,7 +38,8 @@ __device__ __forceinline__ uint32_t mas_hi(uint32_t x, uint64_t mul, uint64_t ad
     return (uint32_t)(lo >> 32) + (uint32_t)(mul >> 32) * x;
 }
 
-__device__ __forceinline__ uint32_t top_bits(uint32_t h, uint32_t m) { return m ? h >> (32u - m) : 0u; }
+// Top bits of a 32-bit hash value; sh is (32 - bits) mod 32 (see Consts::sh_k).
+__device__ __forceinline__ uint32_t top_bits(uint32_t h, uint32_t sh) { return h >> sh; }
 
 // Eq. 2: Idx(i, LP) = IBN(i) consecutive bits of LP starting at ISB(i), wrapping modulo L.
 // Rotating a doubled copy of LP gives the wrapped window in one shift.
@@ -62,6 +65,16 @@ __device__ __forceinline__ uint32_t seav_byte(uint32_t hip, uint32_t i, const Co
     uint32_t rp = hip & k.rmask;
     uint32_t lp = (uint32_t)((uint64_t)hip >> k.r);
     return rp * k.sea_bytes + k.row_off[i] + row_index(lp, k.isb[i], k.ibn[i], k.L);
+}
+
+// Workgroups of a launch are dispatched to the XCDs round robin (workgroup i to XCD i mod 8).
+// Renumbering them this way gives each XCD one contiguous range of [0, n), so that neighbouring
+// indices (neighbouring buckets, neighbouring tiles) share one XCD's L2.  Any renumbering is a
+// bijection of [0, n); only cache locality depends on the dispatch order.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t i, uint32_t n) {
+    const uint32_t x = i % kXcds, l = i / kXcds, q = n / kXcds, r = n % kXcds;
+    return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
 // ------------------------------------------------------------------------------ launchers
@@ -116,7 +129,7 @@ struct ApplySlot {
 hipError_t launch_apply(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
                         const uint32_t *metaT, uint32_t n_tiles, uint32_t block, uint32_t unroll, hipStream_t s);
 hipError_t launch_apply_bm(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
-                           const uint32_t *base, uint32_t block, hipStream_t s);
+                           const uint32_t *base, uint32_t block, uint32_t unroll, hipStream_t s);
 hipError_t launch_or_merge(uint32_t *dst, const uint32_t *const *src, uint32_t n_src, uint64_t n_words, hipStream_t s);
 hipError_t launch_max_merge_u16(uint16_t *dst, const uint16_t *const *src, uint32_t n_src, uint64_t n_elems,
                                 hipStream_t s);

@@ -48,11 +48,11 @@ __device__ __forceinline__ bool sampled(uint32_t oip, const Consts &c) {
 __device__ __forceinline__ uint32_t se_bit(uint32_t oip, const Consts &c) { return mas_hi(oip, c.mul[1], c.add[1]) >> 29; }
 
 __device__ __forceinline__ uint32_t ldc_bit(uint32_t oip, const Consts &c) {
-    return top_bits(mas_hi(oip, c.mul[2], c.add[2]), c.log2k);
+    return top_bits(mas_hi(oip, c.mul[2], c.add[2]), c.sh_k);
 }
 
 __device__ __forceinline__ uint32_t ldc_col(uint32_t hip, uint32_t i, const Consts &c) {
-    return top_bits(mas_hi(hip, c.mul[3 + i], c.add[3 + i]), c.log2lc);
+    return top_bits(mas_hi(hip, c.mul[3 + i], c.add[3 + i]), c.sh_lc);
 }
 
 // ------------------------------------------------------------------------------ fill
@@ -213,60 +213,29 @@ __device__ void bucket_offsets(uint32_t *cl, uint32_t *cs, uint32_t nb, uint32_t
     __syncthreads();
 }
 
-// BM = false: each tile writes its items bucket-major into its own region (item j of the tile in
-//             64-bit word j / 3) plus its nb + 1 bucket offsets in meta[tile].
-// BM = true:  the tile's segment for bucket b goes to global item offset off[tile][b] (computed
-//             beforehand from exact per-tile counts), padded to a multiple of 3 items with copies
-//             of its last item, so every bucket's items are contiguous over all tiles.
-template <int LR, int PPT, int BLOCK, bool BM>
-__global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTable bt, SlotTable st,
-                                               uint32_t *__restrict__ items, uint32_t *__restrict__ meta,
-                                               const uint32_t *__restrict__ off) {
-    extern __shared__ uint32_t lds[];
-    const uint32_t nb = g.nb;
-    uint32_t *cl = lds;                  // [nb + 1] LDCA counts, then offsets
-    uint32_t *cs = cl + (nb + 1);        // [nb + 1] SEAV counts, then cursors
-    uint32_t *stage = lds + ((2 * (nb + 1) + 3) & ~3u);  // [cap] bucket-major items (16-byte aligned)
-    uint32_t *samp = stage + g.cap;      // [2 * scap] sampled (hip, H2 bit)
-    uint32_t *misc = samp + 2 * g.scap;  // [0] sampled count, [1..] scan scratch
+// Bit addresses of a tile's pairs: LDCA items are counted per bucket in cl (the returned rank is
+// kept per item), sampled pairs are staged in samp (or recorded directly once samp is full).
+template <int LR, int PPT, int BLOCK, bool FULL>
+__device__ __forceinline__ void bin_hash_pairs(const Consts &c, const BinGeometry &g, const SlotPtrs &S,
+                                               const u32x2 (&pr)[PPT], uint64_t p0, uint64_t n, uint32_t *cl,
+                                               uint32_t *samp, uint32_t *misc, uint32_t (&bits)[PPT * LR],
+                                               uint32_t (&rk)[(PPT * LR + 1) / 2]) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t tile = blockIdx.x;
-    uint32_t bi = 0;
-    while (bi + 1 < bt.n && bt.b[bi + 1].first_tile <= tile) ++bi;
-    const BatchDesc B = bt.b[bi];
-    const SlotPtrs S = st.s[B.slot];
-    const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
-    const uint32_t smask = (1u << g.S) - 1u;
-    const uint32_t seav_base = (uint32_t)c.ldca_bits;   // SEAV bits follow the LDCA bits
-
-    for (uint32_t i = tid; i < 2 * (nb + 1); i += BLOCK) cl[i] = 0;
-    if (tid == 0) misc[0] = 0;
-
-    // every lane loads unconditionally (past-the-end lanes re-read the last pair and are masked
-    // out below), so all PPT loads of a lane are in flight together
-    const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
-    const uint64_t last = B.n - 1;
-    u32x2 pr[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
-        pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
-    }
-    __syncthreads();
-
-    uint32_t key[PPT * LR], pay[PPT * LR];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const bool valid = p0 + (uint64_t)j * BLOCK + tid < B.n;
+        const bool valid = FULL || p0 + (uint64_t)j * BLOCK + tid < n;
         const uint32_t hip = pr[j].x, oip = pr[j].y;
         const uint32_t q = ldc_bit(oip, c);
 #pragma unroll
         for (int r = 0; r < LR; ++r) {
-            uint32_t bit = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
-            uint32_t bkt = bit >> g.S;
-            uint32_t rank = valid ? atomicAdd(&cl[bkt], 1u) : 0u;
-            key[j * LR + r] = valid ? ((bkt << 16) | rank) : 0xFFFFFFFFu;
-            pay[j * LR + r] = bit & smask;
+            const int k = j * LR + r;
+            const uint32_t bit = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
+            const uint32_t rank = valid ? atomicAdd(&cl[bit >> g.S], 1u) : 0xFFFFu;
+            bits[k] = bit;
+            if (k & 1)
+                rk[k / 2] |= rank << 16;
+            else
+                rk[k / 2] = rank;
         }
         if (valid && sampled(oip, c)) {
             const uint32_t b = se_bit(oip, c);
@@ -284,6 +253,65 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
             }
         }
     }
+}
+
+// BM = false: each tile writes its items bucket-major into its own region (item j of the tile in
+//             64-bit word j / 3) plus its nb + 1 bucket offsets in meta[tile].
+// BM = true:  the tile's segment for bucket b goes to global item offset off[tile][b] (computed
+//             beforehand from exact per-tile counts), padded to a multiple of 3 items with copies
+//             of its last item, so every bucket's items are contiguous over all tiles.
+template <int LR, int PPT, int BLOCK, bool BM>
+__global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTable bt, SlotTable st,
+                                               uint32_t *__restrict__ items, uint32_t *__restrict__ meta,
+                                               const uint32_t *__restrict__ off) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t nb = g.nb;
+    uint32_t *cl = lds;                  // [nb + 1] LDCA counts, then offsets
+    uint32_t *cs = cl + (nb + 1);        // [nb + 1] SEAV counts, then cursors
+    uint32_t *stage = lds + ((2 * (nb + 1) + 3) & ~3u);  // [cap] bucket-major items (16-byte aligned)
+    uint32_t *samp = stage + g.cap;      // [2 * scap] sampled (hip, H2 bit)
+    uint32_t *misc = samp + 2 * g.scap;  // [0] sampled count, [1..] scan scratch
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
+    uint32_t bi = 0;
+    while (bi + 1 < bt.n && bt.b[bi + 1].first_tile <= tile) ++bi;
+    const BatchDesc B = bt.b[bi];
+    const SlotPtrs S = st.s[B.slot];
+    const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
+    const uint32_t smask = (1u << g.S) - 1u;
+    const uint32_t seav_base = (uint32_t)c.ldca_bits;   // SEAV bits follow the LDCA bits
+
+    for (uint32_t i = tid; i < 2 * (nb + 1); i += BLOCK) cl[i] = 0;
+    if (tid == 0) misc[0] = 0;
+    // bucket-major: this tile's global offsets of its first two buckets per thread, fetched now so
+    // that their latency hides behind the hashing
+    const uint32_t *ot = BM ? off + (uint64_t)tile * nb : nullptr;
+    uint32_t off_pre[2] = {0u, 0u};
+    if (BM) {
+        if (tid < nb) off_pre[0] = ot[tid];
+        if (tid + BLOCK < nb) off_pre[1] = ot[tid + BLOCK];
+    }
+
+    // every lane loads unconditionally (past-the-end lanes re-read the last pair and are masked
+    // out below), so all PPT loads of a lane are in flight together
+    const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+    const uint64_t last = B.n - 1;
+    u32x2 pr[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
+        pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
+    }
+    __syncthreads();
+
+    // per item: its bit address, and its rank inside its bucket (16 bits, two per register;
+    // 0xFFFF marks a lane past the end of the batch)
+    uint32_t bits[PPT * LR], rk[(PPT * LR + 1) / 2];
+    // a full tile (all but the last of a batch) needs no per-pair range test
+    if (p0 + (uint64_t)(PPT * BLOCK) <= B.n)
+        bin_hash_pairs<LR, PPT, BLOCK, true>(c, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
+    else
+        bin_hash_pairs<LR, PPT, BLOCK, false>(c, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
     __syncthreads();
     // a tile with more sampled pairs than it can stage records all of them directly (the decision
     // depends only on the tile's sampled count, so a counting pass can repeat it)
@@ -311,8 +339,8 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
 
 #pragma unroll
     for (int k = 0; k < PPT * LR; ++k) {
-        uint32_t kk = key[k];
-        if (kk != 0xFFFFFFFFu) stage[cl[kk >> 16] + (kk & 0xFFFFu)] = pay[k];
+        const uint32_t rank = (rk[k / 2] >> (16 * (k & 1))) & 0xFFFFu;
+        if (rank != 0xFFFFu) stage[cl[bits[k] >> g.S] + rank] = bits[k] & smask;
     }
     for (uint32_t e = tid; e < ns; e += BLOCK) {
         const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
@@ -338,23 +366,55 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
         uint32_t *mo = meta + (uint64_t)tile * (nb + 1);
         for (uint32_t i = tid; i <= nb; i += BLOCK) mo[i] = cl[i];
     } else {
-        // the SEAV cursors are no longer needed: reuse them for this tile's global offsets
-        const uint32_t *ot = off + (uint64_t)tile * nb;
-        for (uint32_t b = tid; b < nb; b += BLOCK) cs[b] = ot[b];
+        // this tile's global offsets, prefetched into registers, go to the LDS slots of the (now
+        // unused) SEAV cursors
+        for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) cs[b] = m == 0 ? off_pre[0] : m == 1 ? off_pre[1] : ot[b];
         __syncthreads();
+        // groups of 16 lanes copy one bucket's segment each (padded to whole words with its last
+        // item): every store instruction writes 128 contiguous bytes per group
+        constexpr uint32_t G = 16;
+        const uint32_t grp = tid / G, sub = tid % G;
         uint64_t *out = reinterpret_cast<uint64_t *>(items);
-        const uint32_t lane = tid & 63u, wid = tid / 64u;
-        for (uint32_t b = wid; b < nb; b += BLOCK / 64) {
+        for (uint32_t b = grp; b < nb; b += BLOCK / G) {
             const uint32_t beg = cl[b], cnt = cl[b + 1] - beg;
             if (cnt == 0) continue;
-            const uint32_t last = stage[beg + cnt - 1];
-            const uint64_t w0 = cs[b] / 3;
-            for (uint32_t w = lane; 3 * w < cnt; w += 64) {
+            const uint32_t *sg = stage + beg;
+            const uint32_t last = sg[cnt - 1];
+            uint64_t *o = out + cs[b] / 3;
+            const uint32_t nw = (cnt + 2) / 3;
+            for (uint32_t w = sub; w < nw; w += G) {
                 const uint32_t j = 3 * w;
-                uint64_t v = stage[beg + j];
-                v |= (uint64_t)(j + 1 < cnt ? stage[beg + j + 1] : last) << 21;
-                v |= (uint64_t)(j + 2 < cnt ? stage[beg + j + 2] : last) << 42;
-                out[w0 + w] = v;
+                uint64_t v = sg[j];
+                v |= (uint64_t)(j + 1 < cnt ? sg[j + 1] : last) << 21;
+                v |= (uint64_t)(j + 2 < cnt ? sg[j + 2] : last) << 42;
+                o[w] = v;
+            }
+        }
+    }
+}
+
+// The bucket counts of bin_hash_pairs without keeping the items.
+template <int LR, int PPT, int BLOCK, bool FULL>
+__device__ __forceinline__ void count_hash_pairs(const Consts &c, const BinGeometry &g, const u32x2 (&pr)[PPT],
+                                                 uint64_t p0, uint64_t n, uint32_t *hl, uint32_t *hs, uint32_t *misc) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t seav_base = (uint32_t)c.ldca_bits;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (!FULL && p0 + (uint64_t)j * BLOCK + tid >= n) continue;
+        const uint32_t hip = pr[j].x, oip = pr[j].y;
+        const uint32_t q = ldc_bit(oip, c);
+#pragma unroll
+        for (int r = 0; r < LR; ++r) {
+            uint32_t bit = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
+            atomicAdd(&hl[bit >> g.S], 1u);
+        }
+        if (sampled(oip, c)) {
+            atomicAdd(&misc[0], 1u);
+            const uint32_t b = se_bit(oip, c);
+            for (uint32_t r = 0; r < c.sr; ++r) {
+                uint32_t bit = seav_base + seav_byte(hip, r, c) * 8u + b;
+                atomicAdd(&hs[bit >> g.S], 1u);
             }
         }
     }
@@ -375,7 +435,6 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchT
     while (bi + 1 < bt.n && bt.b[bi + 1].first_tile <= tile) ++bi;
     const BatchDesc B = bt.b[bi];
     const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
-    const uint32_t seav_base = (uint32_t)c.ldca_bits;
     for (uint32_t i = tid; i < 2 * nb; i += BLOCK) hl[i] = 0;
     if (tid == 0) misc[0] = 0;
     const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
@@ -387,25 +446,10 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchT
         pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        if (p0 + (uint64_t)j * BLOCK + tid >= B.n) continue;
-        const uint32_t hip = pr[j].x, oip = pr[j].y;
-        const uint32_t q = ldc_bit(oip, c);
-#pragma unroll
-        for (int r = 0; r < LR; ++r) {
-            uint32_t bit = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
-            atomicAdd(&hl[bit >> g.S], 1u);
-        }
-        if (sampled(oip, c)) {
-            atomicAdd(&misc[0], 1u);
-            const uint32_t b = se_bit(oip, c);
-            for (uint32_t r = 0; r < c.sr; ++r) {
-                uint32_t bit = seav_base + seav_byte(hip, r, c) * 8u + b;
-                atomicAdd(&hs[bit >> g.S], 1u);
-            }
-        }
-    }
+    if (p0 + (uint64_t)(PPT * BLOCK) <= B.n)
+        count_hash_pairs<LR, PPT, BLOCK, true>(c, g, pr, p0, B.n, hl, hs, misc);
+    else
+        count_hash_pairs<LR, PPT, BLOCK, false>(c, g, pr, p0, B.n, hl, hs, misc);
     __syncthreads();
     const bool direct = misc[0] > g.scap;
     uint32_t *co = cnt + (uint64_t)tile * nb;
@@ -599,14 +643,15 @@ hipError_t launch_offsets(const uint32_t *cnt, uint32_t *cntT, uint32_t *offT, u
 
 // Phase 2 of the bucket-major layout: one workgroup per (slot, bucket) streams the bucket's
 // contiguous items (three per 64-bit word) into an LDS bitmap and writes the bucket back.
-template <int BLOCK>
+template <int BLOCK, int U>
 __global__ __launch_bounds__(BLOCK) void k_apply_bm(BinGeometry g, ApplyTable at, const uint64_t *__restrict__ items,
                                                     const uint32_t *__restrict__ base) {
+    // U: 8-byte loads in flight per lane
     extern __shared__ uint32_t bm[];
-    constexpr uint32_t U = 4;
     const uint32_t words = 1u << (g.S - 5);
     const uint32_t tid = threadIdx.x;
-    const uint32_t si = blockIdx.x / g.nb, b = blockIdx.x % g.nb;
+    const uint32_t blk = blockIdx.x;
+    const uint32_t si = blk / g.nb, b = blk % g.nb;
     const ApplySlot A = at.s[si];
     uint32_t *dst = b < g.nb_ldca ? A.ldca + (uint64_t)b * words : A.seav_w + (uint64_t)(b - g.nb_ldca) * words;
     if (A.fresh && b < g.nb_ldca) {
@@ -615,7 +660,7 @@ __global__ __launch_bounds__(BLOCK) void k_apply_bm(BinGeometry g, ApplyTable at
         for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = dst[w];
     }
     __syncthreads();
-    const uint32_t w0 = base[blockIdx.x] / 3, w1 = base[blockIdx.x + 1] / 3;
+    const uint32_t w0 = base[blk] / 3, w1 = base[blk + 1] / 3;
     for (uint32_t w = w0 + tid; w < w1; w += BLOCK * U) {
         uint64_t v[U];
 #pragma unroll
@@ -643,18 +688,29 @@ __global__ __launch_bounds__(BLOCK) void k_apply_bm(BinGeometry g, ApplyTable at
     }
 }
 
+template <int U>
+static void launch_apply_bm_u(const BinGeometry &g, const ApplyTable &at, dim3 grid, uint32_t lds, const uint64_t *it,
+                              const uint32_t *base, uint32_t block, hipStream_t s) {
+    if (block == 1024) hipLaunchKernelGGL((k_apply_bm<1024, U>), grid, dim3(1024), lds, s, g, at, it, base);
+    else if (block == 512) hipLaunchKernelGGL((k_apply_bm<512, U>), grid, dim3(512), lds, s, g, at, it, base);
+    else hipLaunchKernelGGL((k_apply_bm<256, U>), grid, dim3(256), lds, s, g, at, it, base);
+}
+
 hipError_t launch_apply_bm(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
-                           const uint32_t *base, uint32_t block, hipStream_t s) {
+                           const uint32_t *base, uint32_t block, uint32_t unroll, hipStream_t s) {
     ApplyTable at{};
     if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+    if (block != 1024 && block != 512 && block != 256) return hipErrorInvalidConfiguration;
     for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
     const uint32_t lds = (1u << (g.S - 5)) * 4u;
     const uint64_t *it = reinterpret_cast<const uint64_t *>(items);
     dim3 grid(n_slots * g.nb);
-    if (block == 1024) hipLaunchKernelGGL(k_apply_bm<1024>, grid, dim3(1024), lds, s, g, at, it, base);
-    else if (block == 512) hipLaunchKernelGGL(k_apply_bm<512>, grid, dim3(512), lds, s, g, at, it, base);
-    else if (block == 256) hipLaunchKernelGGL(k_apply_bm<256>, grid, dim3(256), lds, s, g, at, it, base);
-    else return hipErrorInvalidConfiguration;
+    switch (unroll) {
+    case 8: launch_apply_bm_u<4>(g, at, grid, lds, it, base, block, s); break;
+    case 16: launch_apply_bm_u<8>(g, at, grid, lds, it, base, block, s); break;
+    case 32: launch_apply_bm_u<16>(g, at, grid, lds, it, base, block, s); break;
+    default: return hipErrorInvalidConfiguration;
+    }
     return hipGetLastError();
 }
 

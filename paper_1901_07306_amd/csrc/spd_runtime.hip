@@ -199,7 +199,7 @@ spd_status derive(const spd_params *p, spd_derived *d, std::string *why) {
 void default_tuning(spd_tuning *t) {
     t->direct_max_pairs = 1u << 18;
     t->bucket_bits = 20;
-    t->tile_pairs = 16384;
+    t->tile_pairs = 8192;
     t->bin_block = 1024;
     t->apply_block = 1024;
     t->direct_block = 256;
@@ -207,8 +207,8 @@ void default_tuning(spd_tuning *t) {
     t->seav_lds = 0;
     t->close_block = 256;
     t->launch_pairs = 0;
-    t->apply_unroll = 8;
-    t->bin_mode = 0;
+    t->apply_unroll = 16;
+    t->bin_mode = 1;
 }
 
 void order_stream(spd_ctx *ctx, hipStream_t s) {
@@ -353,7 +353,7 @@ bool bin_geometry(const spd_ctx *ctx, BinGeometry *g) {
         scap = std::min<uint32_t>((scap + 63) / 64 * 64, T);
         uint32_t cap = T * ctx->p.lr + scap * ctx->p.sr;
         cap = (cap + 5) / 6 * 6;
-        if ((uint64_t)T * ctx->p.lr > 65536) continue;   // per-bucket ranks are 16 bits
+        if ((uint64_t)T * ctx->p.lr > 65535) continue;   // per-bucket ranks are 16 bits, 0xFFFF unused
         const uint64_t stage_off = (2ull * (g->nb + 1) + 3) & ~3ull;   // same layout as k_bin
         const uint64_t lds = 4ull * (stage_off + cap + 2ull * scap + 1 + 17);
         if (lds <= kMaxLds) {
@@ -547,7 +547,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             }
             {
                 ProfScope ps(ctx, SPD_K_APPLY, s);
-                SPD_HIP(ctx, launch_apply_bm(g, as, nsl, ctx->items, base, ctx->tune.apply_block, s));
+                SPD_HIP(ctx, launch_apply_bm(g, as, nsl, ctx->items, base, ctx->tune.apply_block, ctx->tune.apply_unroll, s));
             }
         }
         // later groups of the same call OR into these slots
@@ -781,6 +781,10 @@ spd_status ctx_create(const spd_params *p, uint32_t n_routers, uint32_t n_slots,
     c.rmask = (uint32_t)((1ull << p->r) - 1ull);
     c.log2k = p->log2k;
     c.log2lc = p->log2lc;
+    c.sh_k = (32u - p->log2k) & 31u;
+    c.sh_lc = (32u - p->log2lc) & 31u;
+    if (p->log2lc == 0)   // one column: every LH_i is the constant 0
+        for (uint32_t i = 0; i < p->lr; ++i) c.mul[3 + i] = c.add[3 + i] = 0;
     uint32_t off = 0;
     for (uint32_t i = 0; i < p->sr; ++i) {
         c.isb[i] = ctx->d.isb[i];

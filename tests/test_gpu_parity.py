@@ -24,12 +24,16 @@ if not torch.cuda.is_available():
 import paper_1901_07306_amd as spd  # noqa: E402
 
 DIRECT = dict(direct_max_pairs=1 << 62)
-BINNED_SMALL = dict(direct_max_pairs=0, tile_pairs=2048, bucket_bits=12, bin_block=512, apply_block=256)
+# bin_mode 0: per-tile item regions; the library default is the bucket-major layout (bin_mode 1)
+BINNED_SMALL = dict(direct_max_pairs=0, bin_mode=0, tile_pairs=2048, bucket_bits=12, bin_block=512, apply_block=256,
+                    apply_unroll=8)
 BINNED_DEFAULT = dict(direct_max_pairs=0)
-BINNED_CHUNKED = dict(direct_max_pairs=0, launch_pairs=50_000, tile_pairs=8192)
+BINNED_TILES = dict(direct_max_pairs=0, bin_mode=0)
+BINNED_CHUNKED = dict(direct_max_pairs=0, bin_mode=0, launch_pairs=50_000, tile_pairs=16384, apply_unroll=32)
 BUCKET_MAJOR = dict(direct_max_pairs=0, bin_mode=1)
 BUCKET_MAJOR_SMALL = dict(direct_max_pairs=0, bin_mode=1, tile_pairs=2048, bucket_bits=12, bin_block=512,
                           apply_block=256, launch_pairs=70_000)
+BUCKET_MAJOR_WIDE = dict(direct_max_pairs=0, bin_mode=1, tile_pairs=8192, apply_unroll=32)
 
 
 def detector(mp, n_routers=1, isb=None, ibn=None, **tune):
@@ -49,7 +53,8 @@ PARAMS = {
 
 
 MODES = {"direct": DIRECT, "binned_small": BINNED_SMALL, "binned_default": BINNED_DEFAULT,
-         "binned_chunked": BINNED_CHUNKED, "bucket_major": BUCKET_MAJOR, "bucket_major_small": BUCKET_MAJOR_SMALL}
+         "binned_chunked": BINNED_CHUNKED, "bucket_major": BUCKET_MAJOR, "bucket_major_small": BUCKET_MAJOR_SMALL,
+         "bucket_major_wide": BUCKET_MAJOR_WIDE}
 
 
 @pytest.mark.parametrize("pname", list(PARAMS))
@@ -308,16 +313,19 @@ def test_plain_64m_full_window():
     log("case plain_64m full: oracle")
     ref = oracle_sketch(w.params, win.pairs[0])
     want = ref.detect()
-    log("case plain_64m full: gpu (default tuning, the configuration the benchmark times)")
-    det = detector(w.params)
-    try:
-        det.scan(0, to_dev(win.pairs[0]))
-        assert_same_sketch(det, 0, ref, "plain_64m")
-        got = det.close_window(0)
-        assert_same_report(got, want, "plain_64m")
-        assert len(got) >= 490   # sanity: (nearly) all 500 planted hosts are reported
-    finally:
-        det.close()
+    x = to_dev(win.pairs[0])
+    # default tuning (the configuration the benchmark times), then the per-tile item layout
+    for name, tune in (("default", {}), ("tiles", BINNED_TILES)):
+        log(f"case plain_64m full: gpu {name}")
+        det = detector(w.params, **tune)
+        try:
+            det.scan(0, x)
+            assert_same_sketch(det, 0, ref, f"plain_64m {name}")
+            got = det.close_window(0)
+            assert_same_report(got, want, f"plain_64m {name}")
+            assert len(got) >= 490   # sanity: (nearly) all 500 planted hosts are reported
+        finally:
+            det.close()
 
 
 def test_bucket_major_overflow_tile_records_seav_directly():
@@ -326,7 +334,7 @@ def test_bucket_major_overflow_tile_records_seav_directly():
     mp = st.CONFIGS["plain_64m"].params.replace(theta=8)    # tau = 0: every pair is sampled
     rng = np.random.default_rng(71)
     pairs, _ = heavy_hosts(rng, 40, 1200, noise=30_000)
-    for tune in (BUCKET_MAJOR, BUCKET_MAJOR_SMALL, BINNED_DEFAULT):
+    for tune in (BUCKET_MAJOR, BUCKET_MAJOR_SMALL, BINNED_TILES):
         det = detector(mp, **tune)
         try:
             det.scan(0, to_dev(pairs))
