@@ -67,7 +67,7 @@ class SpdProfile(ctypes.Structure):
 
 class SpdServerConfig(ctypes.Structure):
     _fields_ = [("n_routers", u32), ("max_slots", u32), ("window_pairs", u64), ("hbm_budget_bytes", u64),
-                ("max_group_pairs", u64), ("max_group_batches", u32), ("use_graphs", u32)]
+                ("max_group_pairs", u64), ("max_group_batches", u32), ("use_graphs", u32), ("min_scan_pairs", u64)]
 
 
 class SpdWindowResult(ctypes.Structure):
@@ -399,10 +399,11 @@ class Server:
     windows with next()."""
 
     def __init__(self, params: SpdParams, n_routers: int, window_pairs: int = 0, hbm_budget_bytes: int = 0,
-                 max_slots: int = 0, max_group_pairs: int = 0, max_group_batches: int = 0, use_graphs: bool = True):
+                 max_slots: int = 0, max_group_pairs: int = 0, max_group_batches: int = 0, use_graphs: bool = True,
+                 min_scan_pairs: int = 0):
         self.params = params
         cfg = SpdServerConfig(n_routers, max_slots, window_pairs, hbm_budget_bytes, max_group_pairs,
-                              max_group_batches, 1 if use_graphs else 0)
+                              max_group_batches, 1 if use_graphs else 0, min_scan_pairs)
         h = ctypes.c_void_p()
         st = lib().spd_server_create(ctypes.byref(params), ctypes.byref(cfg), ctypes.byref(h))
         if st != SPD_OK:

@@ -379,6 +379,13 @@ spd_status ensure_aux(spd_ctx *ctx, uint64_t words, hipStream_t s) {
     return SPD_OK;
 }
 
+// Item and offset scratch (32-bit words) of one binned launch over `tiles` tiles.  Bucket-major:
+// padded items per tile <= its items + 2 per bucket, 3 items per 64 bits.
+void scratch_need(const BinGeometry &g, uint32_t bin_mode, uint64_t tiles, uint64_t *items_words, uint64_t *meta_words) {
+    *items_words = bin_mode == 0 ? tiles * g.region : (tiles * (g.cap + 2ull * g.nb) + 2) / 3 * 2 + 4;
+    *meta_words = tiles * (g.nb + 1);
+}
+
 spd_status ensure_scratch(spd_ctx *ctx, uint64_t items_words, uint64_t meta_words, hipStream_t s) {
     if (items_words > ctx->items_words || meta_words > ctx->meta_words) SPD_HIP(ctx, hipStreamSynchronize(s));
     if (items_words > ctx->items_words) {
@@ -503,8 +510,10 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
         }
         i0 = i;
         if (nbd == 0) continue;
+        uint64_t items_words, meta_words;
+        scratch_need(g, ctx->tune.bin_mode, tiles, &items_words, &meta_words);
         if (ctx->tune.bin_mode == 0) {
-            spd_status st = ensure_scratch(ctx, (uint64_t)tiles * g.region, (uint64_t)tiles * (g.nb + 1), s);
+            spd_status st = ensure_scratch(ctx, items_words, meta_words, s);
             if (st) return st;
             {
                 ProfScope ps(ctx, SPD_K_BIN, s);
@@ -520,10 +529,9 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                                           ctx->tune.apply_unroll, s));
             }
         } else {
-            // bucket-major: padded items per tile <= its items + 2 per bucket; 3 items per 64 bits
-            const uint64_t max_items = (uint64_t)tiles * (g.cap + 2ull * g.nb);
-            if (max_items >= (1ull << 32)) return fail(ctx, SPD_E_INVALID, "launch too large for 32-bit item offsets");
-            spd_status st = ensure_scratch(ctx, (max_items + 2) / 3 * 2 + 4, (uint64_t)tiles * (g.nb + 1), s);
+            if ((uint64_t)tiles * (g.cap + 2ull * g.nb) >= (1ull << 32))
+                return fail(ctx, SPD_E_INVALID, "launch too large for 32-bit item offsets");
+            spd_status st = ensure_scratch(ctx, items_words, meta_words, s);
             if (!st) st = ensure_aux(ctx, 2ull * nsl * g.nb + 2, s);
             if (st) return st;
             uint32_t lo[kMaxGroup], hi[kMaxGroup];
@@ -1138,6 +1146,8 @@ struct SrvRouter {
     uint64_t in_window = 0;       // pairs recorded in the open window
     uint32_t window = 0;          // index of the open window
     std::deque<SrvPending> q;
+    uint64_t pending = 0;         // pairs queued in q
+    uint32_t close_pending = 0;   // batches in q that carry a close request
     bool waiting = false;         // counted once per admission wait
 };
 
@@ -1169,6 +1179,7 @@ struct spd_server {
     std::condition_variable cv_work, cv_done;
     std::thread worker;
     bool stop = false;
+    uint32_t flushing = 0;        // drain calls in progress: scan every queued pair regardless of min_scan_pairs
     uint64_t queued = 0;          // batches submitted and not yet fully scanned
     spd_server_stats st{};
     spd_status fault = SPD_OK;    // first error seen by the scheduler
@@ -1273,7 +1284,12 @@ void srv_loop(spd_server *S) {
         for (uint32_t k = 0; k < R && gp < S->cfg.max_group_pairs && group.size() < S->cfg.max_group_batches; ++k) {
             const uint32_t ri = (S->rr + k) % R;
             SrvRouter &r = S->routers[ri];
-            if (r.slot < 0) continue;
+            if (r.slot < 0 || r.q.empty()) continue;
+            // a router's queued pairs are scanned together once there are enough of them (each scan
+            // of a slot reads and writes all its buckets), or when its window can end now
+            const bool due = S->stop || S->flushing || r.close_pending || r.pending >= S->cfg.min_scan_pairs ||
+                             (S->cfg.window_pairs && r.in_window + r.pending >= S->cfg.window_pairs);
+            if (!due) continue;
             while (!r.q.empty() && gp < S->cfg.max_group_pairs && group.size() < S->cfg.max_group_batches) {
                 SrvPending &b = r.q.front();
                 uint64_t room = S->cfg.window_pairs ? S->cfg.window_pairs - r.in_window : UINT64_MAX;
@@ -1285,7 +1301,9 @@ void srv_loop(spd_server *S) {
                 const bool boundary = S->cfg.window_pairs && r.in_window == S->cfg.window_pairs;
                 const bool close = boundary || (whole && (b.flags & SPD_SUBMIT_CLOSE));
                 const Clock::time_point t = b.t;
+                r.pending -= take;
                 if (whole) {
+                    if (b.flags & SPD_SUBMIT_CLOSE) r.close_pending--;
                     r.q.pop_front();
                     S->queued--;
                 } else {
@@ -1367,6 +1385,7 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
     S->cfg = *cfg;
     if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = 4ull << 30;
     if (!S->cfg.max_group_pairs) S->cfg.max_group_pairs = 64ull << 20;
+    if (!S->cfg.min_scan_pairs) S->cfg.min_scan_pairs = 8ull << 20;
     if (!S->cfg.max_group_batches) S->cfg.max_group_batches = kMaxGroup;
     S->cfg.max_group_batches = std::min<uint32_t>(S->cfg.max_group_batches, 4096);
     spd_status st = ctx_create(p, 0, 0, S->cfg.hbm_budget_bytes, &S->ctx);
@@ -1380,7 +1399,10 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
     BinGeometry g{};
     if (bin_geometry(ctx, &g)) {
         const uint64_t tiles = S->cfg.max_group_pairs / g.tile_pairs + S->cfg.max_group_batches + 1;
-        st = ensure_scratch(ctx, tiles * g.region, tiles * (g.nb + 1), nullptr);
+        uint64_t items_words, meta_words;
+        scratch_need(g, ctx->tune.bin_mode, tiles, &items_words, &meta_words);
+        st = ensure_scratch(ctx, items_words, meta_words, nullptr);
+        if (!st && ctx->tune.bin_mode) st = ensure_aux(ctx, 2ull * kMaxGroup * g.nb + 2, nullptr);
         if (st) {
             spd_server_destroy(S);
             return st;
@@ -1429,7 +1451,10 @@ spd_status spd_server_submit(spd_server *S, uint32_t router, const uint32_t *pai
     if (S->fault) return S->fault;
     if (S->stop) return SPD_E_STATE;
     if (n_pairs == 0 && !(flags & SPD_SUBMIT_CLOSE)) return SPD_OK;
-    S->routers[router].q.push_back(SrvPending{pairs_dev, n_pairs, flags, t});
+    SrvRouter &r = S->routers[router];
+    r.q.push_back(SrvPending{pairs_dev, n_pairs, flags, t});
+    r.pending += n_pairs;
+    if (flags & SPD_SUBMIT_CLOSE) r.close_pending++;
     S->queued++;
     S->st.batches++;
     S->st.pairs += n_pairs;
@@ -1474,6 +1499,7 @@ spd_status spd_server_next(spd_server *S, spd_window_result *hdr, spd_superpoint
 spd_status spd_server_drain(spd_server *S) {
     if (!S) return SPD_E_INVALID;
     std::unique_lock<std::mutex> lk(S->mu);
+    S->flushing++;
     S->cv_work.notify_all();
     bool stuck = false;
     S->cv_done.wait(lk, [&] {
@@ -1487,6 +1513,7 @@ spd_status spd_server_drain(spd_server *S) {
         stuck = !movable;
         return stuck;
     });
+    S->flushing--;
     if (S->fault) return S->fault;
     if (stuck) {
         S->err = "all window slots are held by open windows; queued batches cannot be admitted";
