@@ -231,8 +231,8 @@ typedef struct spd_server_config {
     uint32_t max_group_batches;    /* fused launch: at most this many batches (0: 32) */
     uint32_t use_graphs;           /* 1: replay each slot's end-of-window work from a hipGraph */
     uint64_t min_scan_pairs;       /* a router's queued pairs are scanned once this many are queued, its
-                                      window can end, a close is requested, or drain is called (0: 8 Mi;
-                                      1: scan every batch as soon as possible) */
+                                      window can end, a close is requested, or drain is called (0: the
+                                      larger of 8 Mi and window_pairs / 4; 1: scan every batch at once) */
 } spd_server_config;
 
 typedef struct spd_window_result {

@@ -148,6 +148,7 @@ struct CloseArgs {
     uint32_t n_rp;
     uint32_t list_stride;
     uint32_t qcap;
+    uint32_t stage_words;  // LDS words per wavefront holding one SEA (its bit view when sliding)
 };
 hipError_t launch_close(const Consts &c, const CloseArgs &a, bool sliding, uint32_t block, uint32_t grid,
                         hipStream_t s);

@@ -932,8 +932,9 @@ __device__ __forceinline__ uint32_t load_se(const CloseArgs &a, uint64_t byte) {
     return v;
 }
 
+// word < 2^27: a sketch has fewer than 2^32 bits
 template <bool SLIDING>
-__device__ __forceinline__ uint32_t load_ldc_word(const CloseArgs &a, uint64_t word) {
+__device__ __forceinline__ uint32_t load_ldc_word(const CloseArgs &a, uint32_t word) {
     if (!SLIDING) return a.ldca[word];
     const uint16_t *t = a.ldca_ts + word * 32;
     uint32_t v = 0;
@@ -953,23 +954,45 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 
 // ULDC of every queued candidate: AND of its LR LDCs, z0 = k - popcount; report if z0 <= z_theta.
+// Four candidates at a time, 16 lanes each; a lane reads 8 words of each of two LDCs before it
+// waits, so one round trip to memory serves four candidates (k = 4096, LR = 2).
 template <bool SLIDING>
 __device__ void filter_queue(const CloseArgs &a, const Consts &c, const uint32_t *queue, uint32_t qn, uint32_t lane) {
+    constexpr uint32_t G = 16, W = SLIDING ? 2 : 8, RB = SLIDING ? 1 : 2;
     const uint32_t words = 1u << (c.log2k - 5);
-    for (uint32_t e = 0; e < qn; ++e) {
-        const uint32_t h = queue[e];
+    const uint32_t grp = lane / G, sub = lane % G;
+    for (uint32_t e0 = 0; e0 < qn; e0 += 64 / G) {
+        const bool live = e0 + grp < qn;
+        const uint32_t h = queue[live ? e0 + grp : e0];
         uint32_t ones = 0;
-        for (uint32_t w = lane; w < words; w += 64) {
-            uint32_t u = 0xFFFFFFFFu;
-            for (uint32_t r = 0; r < c.lr; ++r) {
-                uint64_t base = ((uint64_t)((r << c.log2lc) | ldc_col(h, r, c))) << (c.log2k - 5);
-                u &= load_ldc_word<SLIDING>(a, base + w);
+        for (uint32_t w0 = 0; w0 < words; w0 += G * W) {
+            uint32_t u[W];
+#pragma unroll
+            for (uint32_t k = 0; k < W; ++k) u[k] = 0xFFFFFFFFu;
+            for (uint32_t r0 = 0; r0 < c.lr; r0 += RB) {
+                uint32_t v[RB][W];
+#pragma unroll
+                for (uint32_t rr = 0; rr < RB; ++rr) {
+                    const uint32_t r = r0 + rr < c.lr ? r0 + rr : c.lr - 1;   // a repeated row is harmless
+                    const uint32_t base = ((r << c.log2lc) | ldc_col(h, r, c)) << (c.log2k - 5);
+#pragma unroll
+                    for (uint32_t k = 0; k < W; ++k) {
+                        const uint32_t w = w0 + k * G + sub;
+                        v[rr][k] = load_ldc_word<SLIDING>(a, base + (w < words ? w : words - 1));
+                    }
+                }
+#pragma unroll
+                for (uint32_t rr = 0; rr < RB; ++rr)
+#pragma unroll
+                    for (uint32_t k = 0; k < W; ++k) u[k] &= v[rr][k];
             }
-            ones += __popc(u);
+#pragma unroll
+            for (uint32_t k = 0; k < W; ++k)
+                if (w0 + k * G + sub < words) ones += __popc(u[k]);
         }
-        ones = wave_sum(ones);
+        for (uint32_t o = G / 2; o > 0; o >>= 1) ones += __shfl_xor(ones, o, 64);
         const uint32_t z0 = (1u << c.log2k) - ones;
-        if (lane == 0 && z0 <= c.z_theta) {
+        if (live && sub == 0 && z0 <= c.z_theta) {
             uint32_t slot = atomicAdd(&a.counters[0], 1u);
             if (slot < a.rec_cap) {
                 a.rec[2 * slot] = h;
@@ -984,15 +1007,31 @@ __global__ __launch_bounds__(BLOCK) void k_close(Consts c, CloseArgs a) {
     extern __shared__ uint32_t lds[];
     constexpr uint32_t NW = BLOCK / 64;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    const uint32_t per_wave = c.sr * a.list_stride + a.qcap;
+    const uint32_t per_wave = c.sr * a.list_stride + a.qcap + a.stage_words;
     uint32_t *lists = lds + wid * per_wave;      // row i: entries (cell << 8 | SE value)
     uint32_t *queue = lists + c.sr * a.list_stride;
+    uint8_t *sea8 = reinterpret_cast<uint8_t *>(queue + a.qcap);   // the SEA of the current RP
+    const bool staged = a.stage_words != 0;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t lmask = (c.L == 32) ? 0xFFFFFFFFull : ((1ull << c.L) - 1ull);
     uint32_t n_cand = 0;
 
     for (uint32_t rp = blockIdx.x * NW + wid; rp < a.n_rp; rp += gridDim.x * NW) {
         const uint64_t sea = (uint64_t)rp * c.sea_bytes;
+        // stage the whole SEA in LDS (when it fits), eight loads in flight per lane
+        auto se_at = [&](uint32_t byte) -> uint32_t { return staged ? sea8[byte] : load_se<SLIDING>(a, sea + byte); };
+        for (uint32_t b0 = 0; staged && b0 < c.sea_bytes; b0 += 64 * 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) {
+                const uint32_t b = b0 + k * 64 + lane;
+                v[k] = load_se<SLIDING>(a, sea + (b < c.sea_bytes ? b : c.sea_bytes - 1));
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k)
+                if (b0 + k * 64 + lane < c.sea_bytes) sea8[b0 + k * 64 + lane] = (uint8_t)v[k];
+        }
+        wave_lds_sync();
         uint32_t cnt[kMaxRows];
         bool empty = false;
         for (uint32_t i = 0; i < c.sr; ++i) {
@@ -1000,7 +1039,7 @@ __global__ __launch_bounds__(BLOCK) void k_close(Consts c, CloseArgs a) {
             uint32_t n_hot = 0;
             for (uint32_t c0 = 0; c0 < cells; c0 += 64) {
                 const uint32_t cell = c0 + lane;
-                uint32_t v = cell < cells ? load_se<SLIDING>(a, sea + c.row_off[i] + cell) : 0u;
+                uint32_t v = cell < cells ? se_at(c.row_off[i] + cell) : 0u;
                 const bool hot = __popc(v) >= kSeHot;
                 const uint64_t bal = __ballot(hot);
                 if (hot) lists[i * a.list_stride + n_hot + __popcll(bal & lane_lt)] = (cell << 8) | v;
@@ -1061,7 +1100,7 @@ __global__ __launch_bounds__(BLOCK) void k_close(Consts c, CloseArgs a) {
                 if (l <= lmask) {
                     uint32_t seu = 0xFFu;
                     for (uint32_t i = 0; i < c.sr; ++i)
-                        seu &= load_se<SLIDING>(a, sea + c.row_off[i] + row_index((uint32_t)l, c.isb[i], c.ibn[i], c.L));
+                        seu &= se_at(c.row_off[i] + row_index((uint32_t)l, c.isb[i], c.ibn[i], c.L));
                     cand = __popc(seu) >= kSeHot;
                 }
                 const uint64_t bal = __ballot(cand);
@@ -1080,11 +1119,19 @@ __global__ __launch_bounds__(BLOCK) void k_close(Consts c, CloseArgs a) {
         n_cand += qn;
         wave_lds_sync();
     }
-    if (lane == 0 && n_cand) atomicAdd(&a.counters[1], n_cand);
+    // one global atomic per workgroup: atomics on one address are serialized device-wide
+    __shared__ uint32_t wave_cand[NW];
+    if (lane == 0) wave_cand[wid] = n_cand;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0;
+        for (uint32_t w = 0; w < NW; ++w) sum += wave_cand[w];
+        if (sum) atomicAdd(&a.counters[1], sum);
+    }
 }
 
 hipError_t launch_close(const Consts &c, const CloseArgs &a, bool sliding, uint32_t block, uint32_t grid, hipStream_t s) {
-    uint32_t lds = (block / 64) * (c.sr * a.list_stride + a.qcap) * 4u;
+    uint32_t lds = (block / 64) * (c.sr * a.list_stride + a.qcap + a.stage_words) * 4u;
     if (block == 256) {
         if (sliding) hipLaunchKernelGGL((k_close<true, 256>), dim3(grid), dim3(256), lds, s, c, a);
         else hipLaunchKernelGGL((k_close<false, 256>), dim3(grid), dim3(256), lds, s, c, a);

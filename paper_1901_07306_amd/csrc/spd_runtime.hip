@@ -617,14 +617,20 @@ spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArg
     for (uint32_t i = 0; i < ctx->p.sr; ++i) max_ibn = std::max(max_ibn, ctx->d.ibn[i]);
     a->list_stride = 1u << max_ibn;
     a->qcap = 256;
+    // each wavefront stages its SEA in LDS when that fits next to the hot lists (else it reads
+    // the SEA from global memory)
+    const uint64_t lists = (uint64_t)ctx->p.sr * a->list_stride + a->qcap;
+    const uint64_t stage = (ctx->d.sea_bytes + 3) / 4;
+    a->stage_words = (lists + stage) * 4ull <= kMaxLds ? (uint32_t)stage : 0u;
+    const uint64_t per_wave = lists + a->stage_words;
     uint32_t b = ctx->tune.close_block;
-    while (b > 64 && (b / 64) * (ctx->p.sr * a->list_stride + a->qcap) * 4ull > kMaxLds) b /= 2;
-    if ((b / 64) * (ctx->p.sr * a->list_stride + a->qcap) * 4ull > kMaxLds)
+    while (b > 64 && (b / 64) * per_wave * 4ull > kMaxLds) b /= 2;
+    if ((b / 64) * per_wave * 4ull > kMaxLds)
         return fail(ctx, SPD_E_INVALID, "SEA rows too large for the end-of-window kernel");
     const uint32_t waves = b / 64;
     const uint64_t want = ((uint64_t)a->n_rp + waves - 1) / waves;
     *block = b;
-    *grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)ctx->n_cu * 16));
+    *grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)ctx->n_cu * 8));
     return SPD_OK;
 }
 
@@ -1385,7 +1391,7 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
     S->cfg = *cfg;
     if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = 4ull << 30;
     if (!S->cfg.max_group_pairs) S->cfg.max_group_pairs = 64ull << 20;
-    if (!S->cfg.min_scan_pairs) S->cfg.min_scan_pairs = 8ull << 20;
+    if (!S->cfg.min_scan_pairs) S->cfg.min_scan_pairs = std::max<uint64_t>(8ull << 20, S->cfg.window_pairs / 4);
     if (!S->cfg.max_group_batches) S->cfg.max_group_batches = kMaxGroup;
     S->cfg.max_group_batches = std::min<uint32_t>(S->cfg.max_group_batches, 4096);
     spd_status st = ctx_create(p, 0, 0, S->cfg.hbm_budget_bytes, &S->ctx);
