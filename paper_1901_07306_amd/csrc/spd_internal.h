@@ -117,8 +117,9 @@ hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *
 hipError_t launch_offsets(const uint32_t *cnt, uint32_t *cntT, uint32_t *offT, uint32_t *off, uint32_t *tot,
                           uint32_t *base, const uint32_t *tile_lo, const uint32_t *tile_hi, uint32_t n_slots,
                           uint32_t nb, uint32_t n_tiles, hipStream_t s);
-hipError_t launch_bin_bm(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
-                         uint32_t n_tiles, uint32_t *items, const uint32_t *off, const SlotPtrs *slots, hipStream_t s);
+hipError_t launch_place(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+                        uint32_t n_tiles, uint32_t *items, const uint32_t *cnt, const uint32_t *off,
+                        const SlotPtrs *slots, hipStream_t s);
 struct ApplySlot {
     uint32_t *ldca;
     uint32_t *seav_w;

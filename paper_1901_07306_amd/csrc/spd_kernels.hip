@@ -55,6 +55,28 @@ __device__ __forceinline__ uint32_t ldc_col(uint32_t hip, uint32_t i, const Cons
     return top_bits(mas_hi(hip, c.mul[3 + i], c.add[3 + i]), c.sh_lc);
 }
 
+// Per-row SEAV constants (ISB, IBN, byte offset of the row in a SEA) copied to LDS by one thread
+// with constant indices: loops over a runtime row count then read LDS instead of indexing the
+// kernel-argument block, which would otherwise be copied to scratch memory.
+struct RowLds {
+    uint32_t v[3 * kMaxRows];
+};
+__device__ __forceinline__ void rows_to_lds(RowLds &rl, const Consts &c) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kMaxRows; ++k) {
+            rl.v[3 * k] = c.isb[k];
+            rl.v[3 * k + 1] = c.ibn[k];
+            rl.v[3 * k + 2] = c.row_off[k];
+        }
+    }
+}
+__device__ __forceinline__ uint32_t seav_byte_l(uint32_t hip, uint32_t i, const RowLds &rl, const Consts &c) {
+    const uint32_t rp = hip & c.rmask;
+    const uint32_t lp = (uint32_t)((uint64_t)hip >> c.r);
+    return rp * c.sea_bytes + rl.v[3 * i + 2] + row_index(lp, rl.v[3 * i], rl.v[3 * i + 1], c.L);
+}
+
 // ------------------------------------------------------------------------------ fill
 __global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
     uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -154,7 +176,9 @@ __global__ __launch_bounds__(1024) void k_scan_stamp(Consts c, BatchTable bt, Sl
             for (uint32_t r = 0; r < c.lr; ++r) S.ldca_ts[ldca_bit(r, ldc_col(hip, r, c), q, c)] = v;
             if (sampled(oip, c)) {
                 const uint32_t b = se_bit(oip, c);
-                for (uint32_t r = 0; r < c.sr; ++r) S.seav_ts[(uint64_t)seav_byte(hip, r, c) * 8u + b] = v;
+                for (uint32_t r = 0; r < c.sr; ++r) {
+                    S.seav_ts[(uint64_t)seav_byte(hip, r, c) * 8u + b] = v;
+                }
             }
         }
     }
@@ -216,7 +240,7 @@ __device__ void bucket_offsets(uint32_t *cl, uint32_t *cs, uint32_t nb, uint32_t
 // Bit addresses of a tile's pairs: LDCA items are counted per bucket in cl (the returned rank is
 // kept per item), sampled pairs are staged in samp (or recorded directly once samp is full).
 template <int LR, int PPT, int BLOCK, bool FULL>
-__device__ __forceinline__ void bin_hash_pairs(const Consts &c, const BinGeometry &g, const SlotPtrs &S,
+__device__ __forceinline__ void bin_hash_pairs(const Consts &c, const RowLds &rl, const BinGeometry &g, const SlotPtrs &S,
                                                const u32x2 (&pr)[PPT], uint64_t p0, uint64_t n, uint32_t *cl,
                                                uint32_t *samp, uint32_t *misc, uint32_t (&bits)[PPT * LR],
                                                uint32_t (&rk)[(PPT * LR + 1) / 2]) {
@@ -247,7 +271,7 @@ __device__ __forceinline__ void bin_hash_pairs(const Consts &c, const BinGeometr
                 // more sampled pairs than the tile reserved: record them directly
                 uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
                 for (uint32_t r = 0; r < c.sr; ++r) {
-                    uint32_t bit = seav_byte(hip, r, c) * 8u + b;
+                    uint32_t bit = seav_byte_l(hip, r, rl, c) * 8u + b;
                     global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
                 }
             }
@@ -255,16 +279,14 @@ __device__ __forceinline__ void bin_hash_pairs(const Consts &c, const BinGeometr
     }
 }
 
-// BM = false: each tile writes its items bucket-major into its own region (item j of the tile in
-//             64-bit word j / 3) plus its nb + 1 bucket offsets in meta[tile].
-// BM = true:  the tile's segment for bucket b goes to global item offset off[tile][b] (computed
-//             beforehand from exact per-tile counts), padded to a multiple of 3 items with copies
-//             of its last item, so every bucket's items are contiguous over all tiles.
-template <int LR, int PPT, int BLOCK, bool BM>
+// Each tile writes its items bucket-major into its own region (item j of the tile in 64-bit word
+// j / 3) plus its nb + 1 bucket offsets in meta[tile].
+template <int LR, int PPT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTable bt, SlotTable st,
-                                               uint32_t *__restrict__ items, uint32_t *__restrict__ meta,
-                                               const uint32_t *__restrict__ off) {
+                                               uint32_t *__restrict__ items, uint32_t *__restrict__ meta) {
     extern __shared__ uint32_t lds[];
+    __shared__ RowLds rl;   // read after the first barrier
+    rows_to_lds(rl, c);
     const uint32_t nb = g.nb;
     uint32_t *cl = lds;                  // [nb + 1] LDCA counts, then offsets
     uint32_t *cs = cl + (nb + 1);        // [nb + 1] SEAV counts, then cursors
@@ -283,15 +305,6 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
 
     for (uint32_t i = tid; i < 2 * (nb + 1); i += BLOCK) cl[i] = 0;
     if (tid == 0) misc[0] = 0;
-    // bucket-major: this tile's global offsets of its first two buckets per thread, fetched now so
-    // that their latency hides behind the hashing
-    const uint32_t *ot = BM ? off + (uint64_t)tile * nb : nullptr;
-    uint32_t off_pre[2] = {0u, 0u};
-    if (BM) {
-        if (tid < nb) off_pre[0] = ot[tid];
-        if (tid + BLOCK < nb) off_pre[1] = ot[tid + BLOCK];
-    }
-
     // every lane loads unconditionally (past-the-end lanes re-read the last pair and are masked
     // out below), so all PPT loads of a lane are in flight together
     const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
@@ -309,9 +322,9 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
     uint32_t bits[PPT * LR], rk[(PPT * LR + 1) / 2];
     // a full tile (all but the last of a batch) needs no per-pair range test
     if (p0 + (uint64_t)(PPT * BLOCK) <= B.n)
-        bin_hash_pairs<LR, PPT, BLOCK, true>(c, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
+        bin_hash_pairs<LR, PPT, BLOCK, true>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
     else
-        bin_hash_pairs<LR, PPT, BLOCK, false>(c, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
+        bin_hash_pairs<LR, PPT, BLOCK, false>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
     __syncthreads();
     // a tile with more sampled pairs than it can stage records all of them directly (the decision
     // depends only on the tile's sampled count, so a counting pass can repeat it)
@@ -321,7 +334,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
         for (uint32_t e = tid; e < g.scap; e += BLOCK) {
             const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
             for (uint32_t r = 0; r < c.sr; ++r) {
-                uint32_t bit = seav_byte(hip, r, c) * 8u + b;
+                uint32_t bit = seav_byte_l(hip, r, rl, c) * 8u + b;
                 global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
             }
         }
@@ -330,7 +343,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
     for (uint32_t e = tid; e < ns; e += BLOCK) {
         const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
         for (uint32_t r = 0; r < c.sr; ++r) {
-            uint32_t bit = seav_base + seav_byte(hip, r, c) * 8u + b;
+            uint32_t bit = seav_base + seav_byte_l(hip, r, rl, c) * 8u + b;
             atomicAdd(&cs[bit >> g.S], 1u);
         }
     }
@@ -345,76 +358,48 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
     for (uint32_t e = tid; e < ns; e += BLOCK) {
         const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
         for (uint32_t r = 0; r < c.sr; ++r) {
-            uint32_t bit = seav_base + seav_byte(hip, r, c) * 8u + b;
+            uint32_t bit = seav_base + seav_byte_l(hip, r, rl, c) * 8u + b;
             uint32_t pos = atomicAdd(&cs[bit >> g.S], 1u);
             stage[pos] = bit & smask;
         }
     }
     __syncthreads();
     // items are at most 21 bits (S <= 20): three per 64-bit word
-    if (!BM) {
-        const uint32_t total = cl[nb];
-        uint64_t *out = reinterpret_cast<uint64_t *>(items + (uint64_t)tile * g.region);
-        const uint32_t n64 = (total + 2) / 3;
-        for (uint32_t i = tid; i < n64; i += BLOCK) {
-            const uint32_t j = 3 * i;
-            uint64_t v = stage[j];
-            if (j + 1 < total) v |= (uint64_t)stage[j + 1] << 21;
-            if (j + 2 < total) v |= (uint64_t)stage[j + 2] << 42;
-            out[i] = v;
-        }
-        uint32_t *mo = meta + (uint64_t)tile * (nb + 1);
-        for (uint32_t i = tid; i <= nb; i += BLOCK) mo[i] = cl[i];
-    } else {
-        // this tile's global offsets, prefetched into registers, go to the LDS slots of the (now
-        // unused) SEAV cursors
-        for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) cs[b] = m == 0 ? off_pre[0] : m == 1 ? off_pre[1] : ot[b];
-        __syncthreads();
-        // groups of 16 lanes copy one bucket's segment each (padded to whole words with its last
-        // item): every store instruction writes 128 contiguous bytes per group
-        constexpr uint32_t G = 16;
-        const uint32_t grp = tid / G, sub = tid % G;
-        uint64_t *out = reinterpret_cast<uint64_t *>(items);
-        for (uint32_t b = grp; b < nb; b += BLOCK / G) {
-            const uint32_t beg = cl[b], cnt = cl[b + 1] - beg;
-            if (cnt == 0) continue;
-            const uint32_t *sg = stage + beg;
-            const uint32_t last = sg[cnt - 1];
-            uint64_t *o = out + cs[b] / 3;
-            const uint32_t nw = (cnt + 2) / 3;
-            for (uint32_t w = sub; w < nw; w += G) {
-                const uint32_t j = 3 * w;
-                uint64_t v = sg[j];
-                v |= (uint64_t)(j + 1 < cnt ? sg[j + 1] : last) << 21;
-                v |= (uint64_t)(j + 2 < cnt ? sg[j + 2] : last) << 42;
-                o[w] = v;
-            }
-        }
+    const uint32_t total = cl[nb];
+    uint64_t *out = reinterpret_cast<uint64_t *>(items + (uint64_t)tile * g.region);
+    const uint32_t n64 = (total + 2) / 3;
+    for (uint32_t i = tid; i < n64; i += BLOCK) {
+        const uint32_t j = 3 * i;
+        uint64_t v = stage[j];
+        if (j + 1 < total) v |= (uint64_t)stage[j + 1] << 21;
+        if (j + 2 < total) v |= (uint64_t)stage[j + 2] << 42;
+        out[i] = v;
     }
+    uint32_t *mo = meta + (uint64_t)tile * (nb + 1);
+    for (uint32_t i = tid; i <= nb; i += BLOCK) mo[i] = cl[i];
 }
 
-// The bucket counts of bin_hash_pairs without keeping the items.
-template <int LR, int PPT, int BLOCK, bool FULL>
+// The bucket counts of bin_hash_pairs without keeping the items.  NEEDQ = false: a bucket holds
+// whole LDCs (at least k bits), so its index does not depend on H3.
+template <int LR, int PPT, int BLOCK, bool FULL, bool NEEDQ>
 __device__ __forceinline__ void count_hash_pairs(const Consts &c, const BinGeometry &g, const u32x2 (&pr)[PPT],
-                                                 uint64_t p0, uint64_t n, uint32_t *hl, uint32_t *hs, uint32_t *misc) {
+                                                 uint64_t p0, uint64_t n, uint32_t *hl, uint32_t *samp, uint32_t *misc) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t seav_base = (uint32_t)c.ldca_bits;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         if (!FULL && p0 + (uint64_t)j * BLOCK + tid >= n) continue;
         const uint32_t hip = pr[j].x, oip = pr[j].y;
-        const uint32_t q = ldc_bit(oip, c);
+        const uint32_t q = NEEDQ ? ldc_bit(oip, c) : 0u;
 #pragma unroll
         for (int r = 0; r < LR; ++r) {
             uint32_t bit = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
             atomicAdd(&hl[bit >> g.S], 1u);
         }
-        if (sampled(oip, c)) {
-            atomicAdd(&misc[0], 1u);
-            const uint32_t b = se_bit(oip, c);
-            for (uint32_t r = 0; r < c.sr; ++r) {
-                uint32_t bit = seav_base + seav_byte(hip, r, c) * 8u + b;
-                atomicAdd(&hs[bit >> g.S], 1u);
+        if (sampled(oip, c)) {   // staged; its SR items are counted by the whole workgroup later
+            const uint32_t e = atomicAdd(&misc[0], 1u);
+            if (e < g.scap) {
+                samp[2 * e] = hip;
+                samp[2 * e + 1] = se_bit(oip, c);
             }
         }
     }
@@ -425,10 +410,13 @@ __device__ __forceinline__ void count_hash_pairs(const Consts &c, const BinGeome
 template <int LR, int PPT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchTable bt, uint32_t *__restrict__ cnt) {
     extern __shared__ uint32_t lds[];
+    __shared__ RowLds rl;   // read after the first barrier
+    rows_to_lds(rl, c);
     const uint32_t nb = g.nb;
     uint32_t *hl = lds;              // [nb] LDCA items
     uint32_t *hs = hl + nb;          // [nb] SEAV items
     uint32_t *misc = hs + nb;        // [0] sampled pairs
+    uint32_t *samp = misc + 1;       // [2 * scap] sampled (hip, H2 bit)
     const uint32_t tid = threadIdx.x;
     const uint32_t tile = blockIdx.x;
     uint32_t bi = 0;
@@ -446,28 +434,204 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchT
         pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
     }
     __syncthreads();
-    if (p0 + (uint64_t)(PPT * BLOCK) <= B.n)
-        count_hash_pairs<LR, PPT, BLOCK, true>(c, g, pr, p0, B.n, hl, hs, misc);
-    else
-        count_hash_pairs<LR, PPT, BLOCK, false>(c, g, pr, p0, B.n, hl, hs, misc);
+    const bool full = p0 + (uint64_t)(PPT * BLOCK) <= B.n;
+    if (g.S < c.log2k) {
+        if (full) count_hash_pairs<LR, PPT, BLOCK, true, true>(c, g, pr, p0, B.n, hl, samp, misc);
+        else count_hash_pairs<LR, PPT, BLOCK, false, true>(c, g, pr, p0, B.n, hl, samp, misc);
+    } else {
+        if (full) count_hash_pairs<LR, PPT, BLOCK, true, false>(c, g, pr, p0, B.n, hl, samp, misc);
+        else count_hash_pairs<LR, PPT, BLOCK, false, false>(c, g, pr, p0, B.n, hl, samp, misc);
+    }
     __syncthreads();
-    const bool direct = misc[0] > g.scap;
+    const uint32_t ns = misc[0];
+    const bool direct = ns > g.scap;
+    if (!direct) {
+        // one thread per (sampled pair, row)
+        const uint32_t seav_base = (uint32_t)c.ldca_bits;
+        for (uint32_t w = tid; w < ns * c.sr; w += BLOCK) {
+            const uint32_t e = w / c.sr, r = w - e * c.sr;
+            const uint32_t bit = seav_base + seav_byte_l(samp[2 * e], r, rl, c) * 8u + samp[2 * e + 1];
+            atomicAdd(&hs[bit >> g.S], 1u);
+        }
+        __syncthreads();
+    }
     uint32_t *co = cnt + (uint64_t)tile * nb;
     for (uint32_t b = tid; b < nb; b += BLOCK) co[b] = hl[b] + (direct ? 0u : hs[b]);
 }
 
-// kind: 0 = k_bin (tile regions), 1 = k_bin (bucket-major), 2 = k_count
+// Bit addresses of a tile's pairs placed straight into their bucket's segment of the stage: the
+// cursors start at the segment bases, so the returning LDS atomic gives the final position.  All
+// of a lane's LDCA bit addresses are computed first and all their atomics issued together, so the
+// LDS round trips overlap; sampled pairs (about one in 2^tau) follow.
+template <int LR, int PPT, int BLOCK, bool FULL>
+__device__ __forceinline__ void place_hash_pairs(const Consts &c, const RowLds &rl, const BinGeometry &g, const SlotPtrs &S,
+                                                 const u32x2 (&pr)[PPT], uint64_t p0, uint64_t n, uint32_t *cur,
+                                                 uint32_t *stage, uint32_t *samp, uint32_t *nsamp) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t smask = (1u << g.S) - 1u;
+    // pairs in chunks of CH: a chunk's LR * CH atomics are in flight together
+    constexpr int CH = PPT < 4 ? PPT : 4;
+#pragma unroll
+    for (int j0 = 0; j0 < PPT; j0 += CH) {
+        uint32_t bits[CH * LR], pos[CH * LR];
+        uint32_t valid = 0;
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+            const int j = j0 + jj;
+            const bool v = FULL || p0 + (uint64_t)j * BLOCK + tid < n;
+            valid |= (uint32_t)v << jj;
+            const uint32_t hip = pr[j].x, oip = pr[j].y;
+            const uint32_t q = ldc_bit(oip, c);
+#pragma unroll
+            for (int r = 0; r < LR; ++r) bits[jj * LR + r] = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
+            if (v && sampled(oip, c)) {   // staged; placed by the whole workgroup later
+                const uint32_t e = atomicAdd(nsamp, 1u);
+                const uint32_t b = se_bit(oip, c);
+                if (e < g.scap) {
+                    samp[2 * e] = hip;
+                    samp[2 * e + 1] = b;
+                } else {
+                    // only a tile whose SEAV items were left out of the counts gets here
+                    uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
+                    for (uint32_t r = 0; r < c.sr; ++r) {
+                        const uint32_t bit = seav_byte_l(hip, r, rl, c) * 8u + b;
+                        global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH * LR; ++k)
+            pos[k] = (FULL || ((valid >> (k / LR)) & 1u)) ? atomicAdd(&cur[bits[k] >> g.S], 1u) : 0u;
+#pragma unroll
+        for (int k = 0; k < CH * LR; ++k)
+            if (FULL || ((valid >> (k / LR)) & 1u)) stage[pos[k]] = bits[k] & smask;
+    }
+}
+
+// Bucket-major binning (after k_count and the offset scans): a workgroup re-reads a tile, builds
+// its padded segment bases from the tile's exact counts (cnt[tile]), places every item directly
+// at its final position in an LDS stage, pads each segment to whole 64-bit words with copies of
+// its last item, and writes segment b to global item offset off[tile][b].  A tile whose SEAV
+// items were left out of the counts (more sampled pairs than the stage reserves) records them with
+// global atomics instead, exactly as k_count decided.
+template <int LR, int PPT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchTable bt, SlotTable st,
+                                                 uint64_t *__restrict__ items, const uint32_t *__restrict__ cnt,
+                                                 const uint32_t *__restrict__ off) {
+    extern __shared__ uint32_t lds[];
+    __shared__ RowLds rl;   // read after the first barrier
+    rows_to_lds(rl, c);
+    const uint32_t nb = g.nb;
+    uint32_t *cur = lds;                 // [nb + 1] padded counts, then cursors, then global offsets
+    uint32_t *lb = cur + (nb + 1);       // [nb + 1] segment bases in the stage; lb[nb] = padded total
+    uint32_t *stage = lds + ((2 * (nb + 1) + 3) & ~3u);   // [cap]
+    uint32_t *misc = stage + g.cap;      // [0..16] scan scratch, [17] sampled pairs
+    uint32_t *samp = misc + 18;          // [2 * scap] sampled (hip, H2 bit)
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
+    uint32_t bi = 0;
+    while (bi + 1 < bt.n && bt.b[bi + 1].first_tile <= tile) ++bi;
+    const BatchDesc B = bt.b[bi];
+    const SlotPtrs S = st.s[B.slot];
+    const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
+
+    // counts and global offsets of this tile (two per thread held in registers), and the pairs:
+    // every load is issued before the first wait
+    const uint32_t *ct = cnt + (uint64_t)tile * nb;
+    const uint32_t *ot = off + (uint64_t)tile * nb;
+    uint32_t c_pre[2] = {0u, 0u}, o_pre[2] = {0u, 0u};
+    if (tid < nb) {
+        c_pre[0] = ct[tid];
+        o_pre[0] = ot[tid];
+    }
+    if (tid + BLOCK < nb) {
+        c_pre[1] = ct[tid + BLOCK];
+        o_pre[1] = ot[tid + BLOCK];
+    }
+    const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+    const uint64_t last = B.n - 1;
+    u32x2 pr[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
+        pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
+    }
+    for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
+        const uint32_t v = m == 0 ? c_pre[0] : m == 1 ? c_pre[1] : ct[b];
+        cur[b] = (v + 2) / 3 * 3;
+        lb[b] = 0;
+    }
+    if (tid == 0) {
+        cur[nb] = lb[nb] = 0;
+        misc[17] = 0;
+    }
+    __syncthreads();
+    // exclusive scan of the padded counts (lb is all zero: bucket_offsets adds cur[b] + lb[b])
+    bucket_offsets<BLOCK>(cur, lb, nb, misc);
+    // bucket_offsets leaves cur[b] = base, lb[b] = base + padded count (= the next base)
+    for (uint32_t b = tid; b <= nb; b += BLOCK) {
+        const uint32_t base = cur[b];
+        lb[b] = base;
+    }
+    __syncthreads();
+    const bool seav_direct = lb[nb] == lb[g.nb_ldca];   // no SEAV items were counted for this tile
+    if (p0 + (uint64_t)(PPT * BLOCK) <= B.n)
+        place_hash_pairs<LR, PPT, BLOCK, true>(c, rl, g, S, pr, p0, B.n, cur, stage, samp, misc + 17);
+    else
+        place_hash_pairs<LR, PPT, BLOCK, false>(c, rl, g, S, pr, p0, B.n, cur, stage, samp, misc + 17);
+    __syncthreads();
+    // the staged sampled pairs: one thread per (pair, row)
+    {
+        const uint32_t ns = misc[17] < g.scap ? misc[17] : g.scap;
+        const uint32_t smask = (1u << g.S) - 1u;
+        const uint32_t seav_base = (uint32_t)c.ldca_bits;
+        uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
+        for (uint32_t w = tid; w < ns * c.sr; w += BLOCK) {
+            const uint32_t e = w / c.sr, r = w - e * c.sr;
+            const uint32_t byte = seav_byte_l(samp[2 * e], r, rl, c), b = samp[2 * e + 1];
+            if (seav_direct) {
+                const uint32_t bit = byte * 8u + b;
+                global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
+            } else {
+                const uint32_t bit = seav_base + byte * 8u + b;
+                stage[atomicAdd(&cur[bit >> g.S], 1u)] = bit & smask;
+            }
+        }
+    }
+    __syncthreads();
+    // pad every segment to whole words with its last item, then switch cur to global offsets
+    for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
+        const uint32_t e = cur[b], s0 = lb[b], pe = lb[b + 1];
+        if (e > s0)
+            for (uint32_t p = e; p < pe; ++p) stage[p] = stage[e - 1];
+        cur[b] = m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : ot[b];
+    }
+    __syncthreads();
+    // groups of 16 lanes copy one segment each: 128 contiguous bytes per group per store
+    constexpr uint32_t G = 16;
+    const uint32_t grp = tid / G, sub = tid % G;
+    for (uint32_t b = grp; b < nb; b += BLOCK / G) {
+        const uint32_t w0 = lb[b] / 3, nw = (lb[b + 1] - lb[b]) / 3;
+        const uint32_t *sg = stage + 3 * w0;
+        uint64_t *o = items + cur[b] / 3;
+        for (uint32_t w = sub; w < nw; w += G)
+            o[w] = (uint64_t)sg[3 * w] | ((uint64_t)sg[3 * w + 1] << 21) | ((uint64_t)sg[3 * w + 2] << 42);
+    }
+}
+
+// kind: 0 = k_bin (tile regions), 1 = k_place (bucket-major), 2 = k_count
 template <int LR, int PPT, int BLOCK>
 static void launch_bin_t(int kind, const Consts &c, const BinGeometry &g, const BatchTable &bt, const SlotTable &st,
                          uint32_t n_tiles, uint32_t *items, uint32_t *meta, const uint32_t *off, hipStream_t s) {
     if (kind == 0)
-        hipLaunchKernelGGL((k_bin<LR, PPT, BLOCK, false>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st, items,
-                           meta, off);
+        hipLaunchKernelGGL((k_bin<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st, items, meta);
     else if (kind == 1)
-        hipLaunchKernelGGL((k_bin<LR, PPT, BLOCK, true>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st, items,
-                           meta, off);
+        hipLaunchKernelGGL((k_place<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st,
+                           reinterpret_cast<uint64_t *>(items), meta, off);
     else
-        hipLaunchKernelGGL((k_count<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), (2 * g.nb + 1) * 4u, s, c, g, bt, meta);
+        hipLaunchKernelGGL((k_count<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), (2 * g.nb + 1 + 2 * g.scap) * 4u, s, c,
+                           g, bt, meta);
 }
 
 template <int LR>
@@ -510,9 +674,10 @@ hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *ba
     return launch_bin_kind(0, c, g, batches, n_batches, n_tiles, items, meta, nullptr, slots, s);
 }
 
-hipError_t launch_bin_bm(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
-                         uint32_t n_tiles, uint32_t *items, const uint32_t *off, const SlotPtrs *slots, hipStream_t s) {
-    return launch_bin_kind(1, c, g, batches, n_batches, n_tiles, items, nullptr, off, slots, s);
+hipError_t launch_place(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+                        uint32_t n_tiles, uint32_t *items, const uint32_t *cnt, const uint32_t *off,
+                        const SlotPtrs *slots, hipStream_t s) {
+    return launch_bin_kind(1, c, g, batches, n_batches, n_tiles, items, const_cast<uint32_t *>(cnt), off, slots, s);
 }
 
 hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
@@ -530,7 +695,7 @@ struct RangeTable {
 // each rounded up to a multiple of 3 (whole 64-bit words).  offT[b][t] relative to the segment
 // start; tot[slot * nb + b] = the bucket's padded total.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_rowscan(const uint32_t *__restrict__ cntT, uint32_t *__restrict__ offT,
+__global__ __launch_bounds__(BLOCK) void k_rowscan(const uint32_t *cntT, uint32_t *offT,
                                                    uint32_t *__restrict__ tot, RangeTable rt, uint32_t nb,
                                                    uint32_t n_tiles) {
     __shared__ uint32_t wsum[BLOCK / 64 + 1];
@@ -634,7 +799,7 @@ hipError_t launch_offsets(const uint32_t *cnt, uint32_t *cntT, uint32_t *offT, u
     rt.n = n_slots;
     hipError_t e = launch_transpose(cnt, cntT, n_tiles, nb, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rowscan<256>, dim3(n_slots * nb), dim3(256), 0, s, cntT, offT, tot, rt, nb, n_tiles);
+    hipLaunchKernelGGL(k_rowscan<1024>, dim3(n_slots * nb), dim3(1024), 0, s, cntT, offT, tot, rt, nb, n_tiles);
     hipLaunchKernelGGL(k_basescan, dim3(1), dim3(1024), 0, s, tot, base, n_slots * nb);
     dim3 grid((n_tiles + 31) / 32, (nb + 31) / 32);
     hipLaunchKernelGGL(k_offsets, grid, dim3(256), 0, s, offT, base, off, rt, nb, n_tiles);

@@ -71,6 +71,7 @@ struct spd_ctx {
     uint64_t items_words = 0;
     uint32_t *meta = nullptr;
     uint32_t *metaT = nullptr;
+    uint32_t *metaB = nullptr;
     uint64_t meta_words = 0;
     uint32_t *aux = nullptr;         // bucket-major layout: padded bucket totals and their prefix
     uint64_t aux_words = 0;
@@ -348,18 +349,23 @@ bool bin_geometry(const spd_ctx *ctx, BinGeometry *g) {
         if (ppt != 4 && ppt != 8 && ppt != 16) continue;
         // items are held in registers between counting and scattering: keep them spill-free
         if (ppt * ctx->p.lr * g->block > 32u * 1024u) continue;
+        // sampled pairs a tile stages (more are recorded with global atomics): the mean plus
+        // six standard deviations and a margin
         const double expect = (double)T / (double)(1ull << ctx->d.tau);
-        uint32_t scap = (uint32_t)std::ceil(2.0 * expect + 8.0 * std::sqrt(expect) + 64.0);
+        uint32_t scap = (uint32_t)std::ceil(expect + 6.0 * std::sqrt(expect) + 32.0);
         scap = std::min<uint32_t>((scap + 63) / 64 * 64, T);
-        uint32_t cap = T * ctx->p.lr + scap * ctx->p.sr;
+        const bool bm = t.bin_mode != 0;
+        // bucket-major segments are padded to whole words: at most 2 more items per bucket
+        uint64_t cap = (uint64_t)T * ctx->p.lr + (uint64_t)scap * ctx->p.sr + (bm ? 2ull * g->nb : 0ull);
         cap = (cap + 5) / 6 * 6;
         if ((uint64_t)T * ctx->p.lr > 65535) continue;   // per-bucket ranks are 16 bits, 0xFFFF unused
-        const uint64_t stage_off = (2ull * (g->nb + 1) + 3) & ~3ull;   // same layout as k_bin
-        const uint64_t lds = 4ull * (stage_off + cap + 2ull * scap + 1 + 17);
+        const uint64_t stage_off = (2ull * (g->nb + 1) + 3) & ~3ull;   // same layout in k_bin and k_place
+        // + scan scratch (17 words) + the static per-row constants (3 per row)
+        const uint64_t lds = 4ull * (stage_off + cap + 2ull * scap + 1 + 17 + 3ull * kMaxRows);
         if (lds <= kMaxLds) {
             g->tile_pairs = T;
             g->scap = scap;
-            g->cap = cap;
+            g->cap = (uint32_t)cap;
             g->region = cap / 3 * 2;
             g->lds_bytes = (uint32_t)lds;
             return true;
@@ -382,7 +388,7 @@ spd_status ensure_aux(spd_ctx *ctx, uint64_t words, hipStream_t s) {
 // Item and offset scratch (32-bit words) of one binned launch over `tiles` tiles.  Bucket-major:
 // padded items per tile <= its items + 2 per bucket, 3 items per 64 bits.
 void scratch_need(const BinGeometry &g, uint32_t bin_mode, uint64_t tiles, uint64_t *items_words, uint64_t *meta_words) {
-    *items_words = bin_mode == 0 ? tiles * g.region : (tiles * (g.cap + 2ull * g.nb) + 2) / 3 * 2 + 4;
+    *items_words = bin_mode == 0 ? tiles * g.region : (tiles * g.cap + 2) / 3 * 2 + 4;
     *meta_words = tiles * (g.nb + 1);
 }
 
@@ -398,10 +404,11 @@ spd_status ensure_scratch(spd_ctx *ctx, uint64_t items_words, uint64_t meta_word
     if (meta_words > ctx->meta_words) {
         dev_free(ctx, &ctx->meta, ctx->meta_words * 4);
         dev_free(ctx, &ctx->metaT, ctx->meta_words * 4);
+        dev_free(ctx, &ctx->metaB, ctx->meta_words * 4);
         ctx->meta_words = 0;
         spd_status st = dev_alloc(ctx, &ctx->meta, meta_words * 4);
-        if (st) return st;
-        st = dev_alloc(ctx, &ctx->metaT, meta_words * 4);
+        if (!st) st = dev_alloc(ctx, &ctx->metaT, meta_words * 4);
+        if (!st) st = dev_alloc(ctx, &ctx->metaB, meta_words * 4);
         if (st) return st;
         ctx->meta_words = meta_words;
     }
@@ -529,7 +536,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                                           ctx->tune.apply_unroll, s));
             }
         } else {
-            if ((uint64_t)tiles * (g.cap + 2ull * g.nb) >= (1ull << 32))
+            if ((uint64_t)tiles * g.cap >= (1ull << 32))
                 return fail(ctx, SPD_E_INVALID, "launch too large for 32-bit item offsets");
             spd_status st = ensure_scratch(ctx, items_words, meta_words, s);
             if (!st) st = ensure_aux(ctx, 2ull * nsl * g.nb + 2, s);
@@ -546,12 +553,14 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             }
             {
                 ProfScope ps(ctx, SPD_K_OFFSETS, s);
-                SPD_HIP(ctx, launch_offsets(ctx->meta, ctx->metaT, ctx->meta, ctx->metaT, tot, base, lo, hi, nsl, g.nb,
+                // counts stay in meta for k_place; the relative offsets are scanned in place in
+                // metaT; the global offsets go to metaB
+                SPD_HIP(ctx, launch_offsets(ctx->meta, ctx->metaT, ctx->metaT, ctx->metaB, tot, base, lo, hi, nsl, g.nb,
                                             tiles, s));
             }
             {
                 ProfScope ps(ctx, SPD_K_BIN, s);
-                SPD_HIP(ctx, launch_bin_bm(ctx->c, g, bd, nbd, tiles, ctx->items, ctx->metaT, sp, s));
+                SPD_HIP(ctx, launch_place(ctx->c, g, bd, nbd, tiles, ctx->items, ctx->meta, ctx->metaB, sp, s));
             }
             {
                 ProfScope ps(ctx, SPD_K_APPLY, s);
@@ -874,6 +883,7 @@ void spd_destroy(spd_ctx *ctx) {
         dev_free(ctx, &ctx->items, ctx->items_words * 4);
         dev_free(ctx, &ctx->meta, ctx->meta_words * 4);
         dev_free(ctx, &ctx->metaT, ctx->meta_words * 4);
+        dev_free(ctx, &ctx->metaB, ctx->meta_words * 4);
         dev_free(ctx, &ctx->aux, ctx->aux_words * 4);
         close_buf_free(ctx, ctx->cbuf);
         dev_free(ctx, &ctx->view, ctx->view_words * 4);
