@@ -63,6 +63,9 @@ def pct(v, q):
 
 
 def run_detector(spd, torch, params, x, steps, warmup, tune):
+    """Timed region: `steps` back-to-back windows (scan + end of window, the report on the host),
+    the library's HIP-event profiler on.  Then, untimed, the same number of windows with a
+    synchronisation after each scan, for the end-of-window latency alone."""
     det = spd.Detector(params)
     t = det.tuning
     for k, v in tune.items():
@@ -73,22 +76,27 @@ def run_detector(spd, torch, params, x, steps, warmup, tune):
         det.close_window(0)
     torch.cuda.synchronize()
     det.profile_enable(True)
-    close_ms, window_ms = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rec = None
     for _ in range(steps):
+        det.scan(0, x)
+        rec = det.close_window(0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = det.profile()
+    det.profile_enable(False)
+    close_ms, window_ms = [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
         s0 = time.perf_counter()
         det.scan(0, x)
         torch.cuda.synchronize()
         c0 = time.perf_counter()
-        rec = det.close_window(0)
+        det.close_window(0)
         c1 = time.perf_counter()
         close_ms.append((c1 - c0) * 1e3)
         window_ms.append((c1 - s0) * 1e3)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = det.profile()
     stats = det.stats
     det.close()
     return elapsed, close_ms, window_ms, prof, rec, stats

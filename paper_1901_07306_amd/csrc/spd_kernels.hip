@@ -468,7 +468,6 @@ __device__ __forceinline__ void place_hash_pairs(const Consts &c, const RowLds &
                                                  const u32x2 (&pr)[PPT], uint64_t p0, uint64_t n, uint32_t *cur,
                                                  uint32_t *stage, uint32_t *samp, uint32_t *nsamp) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t smask = (1u << g.S) - 1u;
     // pairs in chunks of CH: a chunk's LR * CH atomics are in flight together
     constexpr int CH = PPT < 4 ? PPT : 4;
 #pragma unroll
@@ -505,7 +504,7 @@ __device__ __forceinline__ void place_hash_pairs(const Consts &c, const RowLds &
             pos[k] = (FULL || ((valid >> (k / LR)) & 1u)) ? atomicAdd(&cur[bits[k] >> g.S], 1u) : 0u;
 #pragma unroll
         for (int k = 0; k < CH * LR; ++k)
-            if (FULL || ((valid >> (k / LR)) & 1u)) stage[pos[k]] = bits[k] & smask;
+            if (FULL || ((valid >> (k / LR)) & 1u)) stage[pos[k]] = bits[k];
     }
 }
 
@@ -584,7 +583,6 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchT
     // the staged sampled pairs: one thread per (pair, row)
     {
         const uint32_t ns = misc[17] < g.scap ? misc[17] : g.scap;
-        const uint32_t smask = (1u << g.S) - 1u;
         const uint32_t seav_base = (uint32_t)c.ldca_bits;
         uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
         for (uint32_t w = tid; w < ns * c.sr; w += BLOCK) {
@@ -595,28 +593,28 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchT
                 global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
             } else {
                 const uint32_t bit = seav_base + byte * 8u + b;
-                stage[atomicAdd(&cur[bit >> g.S], 1u)] = bit & smask;
+                stage[atomicAdd(&cur[bit >> g.S], 1u)] = bit;
             }
         }
     }
     __syncthreads();
-    // pad every segment to whole words with its last item, then switch cur to global offsets
+    // pad every segment to whole words with its last item; cur[b] becomes the distance in words
+    // from the segment's place in the stage to its place in the item buffer
     for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
         const uint32_t e = cur[b], s0 = lb[b], pe = lb[b + 1];
         if (e > s0)
             for (uint32_t p = e; p < pe; ++p) stage[p] = stage[e - 1];
-        cur[b] = m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : ot[b];
+        cur[b] = (m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : ot[b]) / 3 - s0 / 3;
     }
     __syncthreads();
-    // groups of 16 lanes copy one segment each: 128 contiguous bytes per group per store
-    constexpr uint32_t G = 16;
-    const uint32_t grp = tid / G, sub = tid % G;
-    for (uint32_t b = grp; b < nb; b += BLOCK / G) {
-        const uint32_t w0 = lb[b] / 3, nw = (lb[b + 1] - lb[b]) / 3;
-        const uint32_t *sg = stage + 3 * w0;
-        uint64_t *o = items + cur[b] / 3;
-        for (uint32_t w = sub; w < nw; w += G)
-            o[w] = (uint64_t)sg[3 * w] | ((uint64_t)sg[3 * w + 1] << 21) | ((uint64_t)sg[3 * w + 2] << 42);
+    // one thread per stage word: the stage holds full bit addresses, so a word's first item names
+    // its bucket; three 21-bit offsets per 64-bit word
+    const uint32_t smask = (1u << g.S) - 1u;
+    const uint32_t nwords = lb[nb] / 3;
+    for (uint32_t w = tid; w < nwords; w += BLOCK) {
+        const uint32_t s0 = stage[3 * w], s1 = stage[3 * w + 1], s2 = stage[3 * w + 2];
+        items[w + cur[s0 >> g.S]] =
+            (uint64_t)(s0 & smask) | ((uint64_t)(s1 & smask) << 21) | ((uint64_t)(s2 & smask) << 42);
     }
 }
 
