@@ -199,6 +199,10 @@ uint32_t spd_current_slice(const spd_ctx *ctx);
  * is bracketed by two HIP events recorded on the launch stream. */
 spd_status spd_profile_enable(spd_ctx *ctx, uint32_t on);
 
+/* Which kernel kinds are timed while profiling is on: bit k selects kind k (SPD_K_*); all by
+ * default.  Timing fewer kinds records fewer events on the stream. */
+spd_status spd_profile_select(spd_ctx *ctx, uint32_t kinds_mask);
+
 /* Totals since the last spd_profile_enable(); waits for the recorded events. */
 spd_status spd_get_profile(spd_ctx *ctx, spd_profile *out);
 

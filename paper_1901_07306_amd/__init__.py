@@ -90,7 +90,7 @@ RECORD = np.dtype([("ip", "<u4"), ("z0", "<u4"), ("est", "<u4"), ("flags", "<u4"
 EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_batches", "spd_merge",
             "spd_close_window", "spd_slide", "spd_export", "spd_import", "spd_export_stamps",
             "spd_current_slice", "spd_get_tuning", "spd_set_tuning", "spd_get_stats", "spd_strerror",
-            "spd_last_error", "spd_profile_enable", "spd_get_profile", "spd_server_create", "spd_server_submit",
+            "spd_last_error", "spd_profile_enable", "spd_profile_select", "spd_get_profile", "spd_server_create", "spd_server_submit",
             "spd_server_next", "spd_server_drain", "spd_server_get_stats", "spd_server_set_tuning",
             "spd_server_last_error", "spd_server_destroy", "spd_server_replay"]
 
@@ -153,6 +153,7 @@ def lib(require_torch: bool = True) -> ctypes.CDLL:
         "spd_set_tuning": (i32, [vp, P(SpdTuning)]),
         "spd_get_stats": (i32, [vp, P(SpdStats)]),
         "spd_profile_enable": (i32, [vp, u32]),
+        "spd_profile_select": (i32, [vp, u32]),
         "spd_get_profile": (i32, [vp, P(SpdProfile)]),
         "spd_server_create": (i32, [P(SpdParams), P(SpdServerConfig), P(vp)]),
         "spd_server_submit": (i32, [vp, u32, vp, u64, u32]),
@@ -319,6 +320,12 @@ def spd_profile_enable(ctx: int, on: bool = True) -> None:
     _check(lib().spd_profile_enable(ctx, 1 if on else 0), ctx)
 
 
+def spd_profile_select(ctx: int, kinds=None) -> None:
+    """Time only the given kernel kinds (names from K_KINDS) while profiling is on; None: all."""
+    mask = 0xFFFFFFFF if kinds is None else sum(1 << K_KINDS.index(k) for k in kinds)
+    _check(lib().spd_profile_select(ctx, mask), ctx)
+
+
 def spd_get_profile(ctx: int) -> dict:
     """{kind: (launches, total device ms)} since the last spd_profile_enable()."""
     p = SpdProfile()
@@ -382,7 +389,8 @@ class Detector:
     def tuning(self, t: SpdTuning):
         spd_set_tuning(self.ctx, t)
 
-    def profile_enable(self, on=True):
+    def profile_enable(self, on=True, kinds=None):
+        spd_profile_select(self.ctx, kinds)
         spd_profile_enable(self.ctx, on)
 
     def profile(self) -> dict:

@@ -87,6 +87,7 @@ struct spd_ctx {
     hipEvent_t order_ev = nullptr;
     // optional per-kernel timing
     bool prof_on = false;
+    uint32_t prof_mask = ~0u;      // kinds timed while profiling is on (bit k: kind k)
     struct Pending {
         int kind;
         hipEvent_t a, b;
@@ -239,7 +240,7 @@ struct ProfScope {
     hipStream_t s;
     hipEvent_t a = nullptr;
     ProfScope(spd_ctx *c, int k, hipStream_t st) : ctx(c), kind(k), s(st) {
-        if (ctx->prof_on) {
+        if (ctx->prof_on && ((ctx->prof_mask >> k) & 1u)) {
             a = prof_event(ctx);
             if (a) (void)hipEventRecord(a, s);
         }
@@ -1076,6 +1077,12 @@ spd_status spd_profile_enable(spd_ctx *ctx, uint32_t on) {
     prof_harvest(ctx);
     ctx->prof = spd_profile{};
     ctx->prof_on = on != 0;
+    return SPD_OK;
+}
+
+spd_status spd_profile_select(spd_ctx *ctx, uint32_t kinds_mask) {
+    if (!ctx) return SPD_E_INVALID;
+    ctx->prof_mask = kinds_mask;
     return SPD_OK;
 }
 
