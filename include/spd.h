@@ -232,11 +232,12 @@ typedef struct spd_server_config {
     uint64_t window_pairs;         /* close a router's window every this many pairs (0: on request only) */
     uint64_t hbm_budget_bytes;     /* device memory for slots and scratch (0: 4 GiB) */
     uint64_t max_group_pairs;      /* fused launch: at most this many pairs (0: 64 Mi) */
-    uint32_t max_group_batches;    /* fused launch: at most this many batches (0: 32) */
+    uint32_t max_group_batches;    /* fused launch: at most this many batches (0: 1024) */
     uint32_t use_graphs;           /* 1: replay each slot's end-of-window work from a hipGraph */
-    uint64_t min_scan_pairs;       /* a router's queued pairs are scanned once this many are queued, its
-                                      window can end, a close is requested, or drain is called (0: the
-                                      larger of 8 Mi and window_pairs / 4; 1: scan every batch at once) */
+    uint64_t min_scan_pairs;       /* while earlier scans are still running on the GPU, a router's queued
+                                      pairs wait until this many are queued, its window can end, a close
+                                      is requested or drain is called; an idle GPU takes whatever is
+                                      queued (0: the larger of 8 Mi and window_pairs / 4) */
 } spd_server_config;
 
 typedef struct spd_window_result {

@@ -112,12 +112,14 @@ hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t
 hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
                       uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s);
 hipError_t launch_transpose(const uint32_t *meta, uint32_t *metaT, uint32_t rows, uint32_t cols, hipStream_t s);
-hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+// Counting and placement of the bucket-major layout: batches_dev is a device array of n_batches
+// descriptors (any number), sorted by first_tile.
+hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
                         uint32_t n_tiles, uint32_t *cnt, hipStream_t s);
 hipError_t launch_offsets(const uint32_t *cnt, uint32_t *cntT, uint32_t *offT, uint32_t *off, uint32_t *tot,
                           uint32_t *base, const uint32_t *tile_lo, const uint32_t *tile_hi, uint32_t n_slots,
                           uint32_t nb, uint32_t n_tiles, hipStream_t s);
-hipError_t launch_place(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+hipError_t launch_place(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
                         uint32_t n_tiles, uint32_t *items, const uint32_t *cnt, const uint32_t *off,
                         const SlotPtrs *slots, hipStream_t s);
 struct ApplySlot {

@@ -23,6 +23,21 @@ struct BatchTable {
     BatchDesc b[kMaxGroup];
     uint32_t n;
 };
+// Batches of a launch in device memory (any number), for the bucket-major kernels.
+struct BatchList {
+    const BatchDesc *b;
+    uint32_t n;
+};
+// Index of the batch that tile belongs to: the last one whose first tile is <= tile.
+__device__ __forceinline__ uint32_t find_batch(const BatchList &bl, uint32_t tile) {
+    uint32_t lo = 0, hi = bl.n;   // b[lo].first_tile <= tile < b[hi].first_tile (b[n] = infinity)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (bl.b[mid].first_tile <= tile) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 struct SlotTable {
     SlotPtrs s[kMaxGroup];
 };
@@ -408,7 +423,7 @@ __device__ __forceinline__ void count_hash_pairs(const Consts &c, const BinGeome
 // Exact per-tile item counts by bucket (the first pass of the bucket-major layout): the same bit
 // addresses as k_bin, counted in LDS, SEAV items left out for tiles that record them directly.
 template <int LR, int PPT, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchTable bt, uint32_t *__restrict__ cnt) {
+__global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchList bl, uint32_t *__restrict__ cnt) {
     extern __shared__ uint32_t lds[];
     __shared__ RowLds rl;   // read after the first barrier
     rows_to_lds(rl, c);
@@ -419,9 +434,7 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchT
     uint32_t *samp = misc + 1;       // [2 * scap] sampled (hip, H2 bit)
     const uint32_t tid = threadIdx.x;
     const uint32_t tile = blockIdx.x;
-    uint32_t bi = 0;
-    while (bi + 1 < bt.n && bt.b[bi + 1].first_tile <= tile) ++bi;
-    const BatchDesc B = bt.b[bi];
+    const BatchDesc B = bl.b[find_batch(bl, tile)];
     const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
     for (uint32_t i = tid; i < 2 * nb; i += BLOCK) hl[i] = 0;
     if (tid == 0) misc[0] = 0;
@@ -515,7 +528,7 @@ __device__ __forceinline__ void place_hash_pairs(const Consts &c, const RowLds &
 // items were left out of the counts (more sampled pairs than the stage reserves) records them with
 // global atomics instead, exactly as k_count decided.
 template <int LR, int PPT, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchTable bt, SlotTable st,
+__global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchList bl, SlotTable st,
                                                  uint64_t *__restrict__ items, const uint32_t *__restrict__ cnt,
                                                  const uint32_t *__restrict__ off) {
     extern __shared__ uint32_t lds[];
@@ -529,9 +542,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchT
     uint32_t *samp = misc + 18;          // [2 * scap] sampled (hip, H2 bit)
     const uint32_t tid = threadIdx.x;
     const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
-    uint32_t bi = 0;
-    while (bi + 1 < bt.n && bt.b[bi + 1].first_tile <= tile) ++bi;
-    const BatchDesc B = bt.b[bi];
+    const BatchDesc B = bl.b[find_batch(bl, tile)];
     const SlotPtrs S = st.s[B.slot];
     const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
 
@@ -618,27 +629,27 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchT
     }
 }
 
-// kind: 0 = k_bin (tile regions), 1 = k_place (bucket-major), 2 = k_count
 template <int LR, int PPT, int BLOCK>
-static void launch_bin_t(int kind, const Consts &c, const BinGeometry &g, const BatchTable &bt, const SlotTable &st,
-                         uint32_t n_tiles, uint32_t *items, uint32_t *meta, const uint32_t *off, hipStream_t s) {
+static void launch_bin_t(int kind, const Consts &c, const BinGeometry &g, const BatchTable &bt, const BatchList &bl,
+                         const SlotTable &st, uint32_t n_tiles, uint32_t *items, uint32_t *meta, const uint32_t *off,
+                         hipStream_t s) {
     if (kind == 0)
         hipLaunchKernelGGL((k_bin<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st, items, meta);
     else if (kind == 1)
-        hipLaunchKernelGGL((k_place<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st,
+        hipLaunchKernelGGL((k_place<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bl, st,
                            reinterpret_cast<uint64_t *>(items), meta, off);
     else
         hipLaunchKernelGGL((k_count<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), (2 * g.nb + 1 + 2 * g.scap) * 4u, s, c,
-                           g, bt, meta);
+                           g, bl, meta);
 }
 
 template <int LR>
 static hipError_t launch_bin_lr(int kind, const Consts &c, const BinGeometry &g, const BatchTable &bt,
-                                const SlotTable &st, uint32_t n_tiles, uint32_t *items, uint32_t *meta,
-                                const uint32_t *off, hipStream_t s) {
+                                const BatchList &bl, const SlotTable &st, uint32_t n_tiles, uint32_t *items,
+                                uint32_t *meta, const uint32_t *off, hipStream_t s) {
     const uint32_t ppt = g.tile_pairs / g.block;
 #define SPD_BIN_CASE(B, P) \
-    else if (g.block == B && ppt == P) launch_bin_t<LR, P, B>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
+    else if (g.block == B && ppt == P) launch_bin_t<LR, P, B>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
     if (false) {
     }
     SPD_BIN_CASE(1024, 16) SPD_BIN_CASE(1024, 8) SPD_BIN_CASE(1024, 4) SPD_BIN_CASE(512, 16) SPD_BIN_CASE(512, 8)
@@ -648,21 +659,30 @@ static hipError_t launch_bin_lr(int kind, const Consts &c, const BinGeometry &g,
     return hipGetLastError();
 }
 
+// kind: 0 = k_bin (tile regions; batches by value, at most kMaxGroup), 1 = k_place (bucket-major),
+// 2 = k_count (both: batches in device memory, any number)
 static hipError_t launch_bin_kind(int kind, const Consts &c, const BinGeometry &g, const BatchDesc *batches,
                                   uint32_t n_batches, uint32_t n_tiles, uint32_t *items, uint32_t *meta,
                                   const uint32_t *off, const SlotPtrs *slots, hipStream_t s) {
     BatchTable bt{};
+    BatchList bl{};
     SlotTable st{};
-    if (n_batches == 0 || n_batches > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
-    for (uint32_t i = 0; i < n_batches; ++i) bt.b[i] = batches[i];
-    bt.n = n_batches;
+    if (n_batches == 0) return hipErrorInvalidValue;
+    if (kind == 0) {
+        if (n_batches > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+        for (uint32_t i = 0; i < n_batches; ++i) bt.b[i] = batches[i];
+        bt.n = n_batches;
+    } else {
+        bl.b = batches;
+        bl.n = n_batches;
+    }
     if (slots)
         for (int i = 0; i < kMaxGroup; ++i) st.s[i] = slots[i];
     switch (c.lr) {
-    case 1: return launch_bin_lr<1>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
-    case 2: return launch_bin_lr<2>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
-    case 3: return launch_bin_lr<3>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
-    case 4: return launch_bin_lr<4>(kind, c, g, bt, st, n_tiles, items, meta, off, s);
+    case 1: return launch_bin_lr<1>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
+    case 2: return launch_bin_lr<2>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
+    case 3: return launch_bin_lr<3>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
+    case 4: return launch_bin_lr<4>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -672,15 +692,15 @@ hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *ba
     return launch_bin_kind(0, c, g, batches, n_batches, n_tiles, items, meta, nullptr, slots, s);
 }
 
-hipError_t launch_place(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+hipError_t launch_place(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
                         uint32_t n_tiles, uint32_t *items, const uint32_t *cnt, const uint32_t *off,
                         const SlotPtrs *slots, hipStream_t s) {
-    return launch_bin_kind(1, c, g, batches, n_batches, n_tiles, items, const_cast<uint32_t *>(cnt), off, slots, s);
+    return launch_bin_kind(1, c, g, batches_dev, n_batches, n_tiles, items, const_cast<uint32_t *>(cnt), off, slots, s);
 }
 
-hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
+hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
                         uint32_t n_tiles, uint32_t *cnt, hipStream_t s) {
-    return launch_bin_kind(2, c, g, batches, n_batches, n_tiles, nullptr, cnt, nullptr, nullptr, s);
+    return launch_bin_kind(2, c, g, batches_dev, n_batches, n_tiles, nullptr, cnt, nullptr, nullptr, s);
 }
 
 // ---- offsets of the bucket-major layout

@@ -51,6 +51,8 @@ struct CloseBuf {
 
 }  // namespace
 
+constexpr uint32_t kBdRing = 4;   // staging slots for the batch descriptors of binned launches
+
 struct spd_ctx {
     spd_params p{};
     spd_derived d{};
@@ -73,6 +75,11 @@ struct spd_ctx {
     uint32_t *metaT = nullptr;
     uint32_t *metaB = nullptr;
     uint64_t meta_words = 0;
+    BatchDesc *bd_host[kBdRing] = {};   // pinned staging of batch descriptors
+    BatchDesc *bd_dev[kBdRing] = {};
+    hipEvent_t bd_ev[kBdRing] = {};     // recorded after the last kernel that reads a slot
+    uint32_t bd_cap = 0;                // descriptors per slot
+    uint32_t bd_next = 0;
     uint32_t *aux = nullptr;         // bucket-major layout: padded bucket totals and their prefix
     uint64_t aux_words = 0;
     CloseBuf cbuf;                  // end-of-window buffers of spd_close_window
@@ -375,6 +382,40 @@ bool bin_geometry(const spd_ctx *ctx, BinGeometry *g) {
     return false;
 }
 
+void free_batch_ring(spd_ctx *ctx) {
+    for (uint32_t k = 0; k < kBdRing; ++k) {
+        if (ctx->bd_ev[k]) (void)hipEventSynchronize(ctx->bd_ev[k]);
+        if (ctx->bd_host[k]) (void)hipHostFree(ctx->bd_host[k]);
+        ctx->bd_host[k] = nullptr;
+        dev_free(ctx, &ctx->bd_dev[k], (uint64_t)ctx->bd_cap * sizeof(BatchDesc));
+    }
+    ctx->bd_cap = 0;
+}
+
+// Copy a launch's batch descriptors to device memory (next slot of the staging ring; the slot's
+// event, recorded after the kernels that read it, guards its reuse).  The caller records
+// bd_ev[bd_next] after its last kernel and advances bd_next.
+spd_status upload_batches(spd_ctx *ctx, const std::vector<BatchDesc> &bd, hipStream_t s, BatchDesc **out) {
+    for (uint32_t k = 0; k < kBdRing; ++k)
+        if (!ctx->bd_ev[k]) SPD_HIP(ctx, hipEventCreateWithFlags(&ctx->bd_ev[k], hipEventDisableTiming));
+    if (bd.size() > ctx->bd_cap) {
+        free_batch_ring(ctx);
+        const uint32_t cap = (uint32_t)std::max<size_t>(1024, (bd.size() + 1023) / 1024 * 1024);
+        for (uint32_t k = 0; k < kBdRing; ++k) {
+            SPD_HIP(ctx, hipHostMalloc((void **)&ctx->bd_host[k], cap * sizeof(BatchDesc), hipHostMallocDefault));
+            spd_status st = dev_alloc(ctx, &ctx->bd_dev[k], (uint64_t)cap * sizeof(BatchDesc));
+            if (st) return st;
+        }
+        ctx->bd_cap = cap;
+    }
+    const uint32_t k = ctx->bd_next;
+    SPD_HIP(ctx, hipEventSynchronize(ctx->bd_ev[k]));
+    std::memcpy(ctx->bd_host[k], bd.data(), bd.size() * sizeof(BatchDesc));
+    SPD_HIP(ctx, hipMemcpyAsync(ctx->bd_dev[k], ctx->bd_host[k], bd.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+    *out = ctx->bd_dev[k];
+    return SPD_OK;
+}
+
 spd_status ensure_aux(spd_ctx *ctx, uint64_t words, hipStream_t s) {
     if (words <= ctx->aux_words) return SPD_OK;
     SPD_HIP(ctx, hipStreamSynchronize(s));
@@ -484,20 +525,24 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             for (uint64_t a = 0; a < w.n; a += lp) split.push_back(WorkItem{w.slot, w.pairs + 2 * a, std::min(lp, w.n - a)});
         ws.swap(split);
     }
-    // binned: launch groups of at most kMaxGroup batches, kMaxGroup slots and launch_pairs pairs
+    // binned: launch groups of at most kMaxGroup slots and launch_pairs pairs; per-tile regions also
+    // take at most kMaxGroup batches per group, the bucket-major layout any number (its counting and
+    // placement kernels run over the group in chunks of kMaxGroup batches, its offsets and apply
+    // once per group, so each slot's buckets are read and written once per group)
+    const bool bm = ctx->tune.bin_mode != 0;
     size_t i0 = 0;
     while (i0 < ws.size()) {
-        BatchDesc bd[kMaxGroup];
+        std::vector<BatchDesc> bd;
         SlotPtrs sp[kMaxGroup] = {};
         ApplySlot as[kMaxGroup] = {};
         Slot *owner[kMaxGroup] = {};
-        uint32_t nbd = 0, nsl = 0, tiles = 0;
+        uint32_t nsl = 0, tiles = 0;
         uint64_t lpairs = 0;
         size_t i = i0;
-        for (; i < ws.size() && nbd < (uint32_t)kMaxGroup; ++i) {
+        for (; i < ws.size() && (bm || bd.size() < (size_t)kMaxGroup); ++i) {
             const WorkItem &w = ws[i];
             if (w.n == 0) continue;
-            if (lp && nbd && lpairs + w.n > lp) break;
+            if (lp && !bd.empty() && lpairs + w.n > lp) break;
             lpairs += w.n;
             if (nsl == 0 || owner[nsl - 1] != w.slot) {
                 if (nsl == (uint32_t)kMaxGroup) break;
@@ -512,11 +557,12 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             }
             const uint64_t nt = (w.n + g.tile_pairs - 1) / g.tile_pairs;
             if ((uint64_t)tiles + nt > 0x7FFFFFFFull) return fail(ctx, SPD_E_INVALID, "batch too large");
-            bd[nbd++] = BatchDesc{w.pairs, w.n, tiles, nsl - 1};
+            bd.push_back(BatchDesc{w.pairs, w.n, tiles, nsl - 1});
             tiles += (uint32_t)nt;
             as[nsl - 1].tile_hi = tiles;
         }
         i0 = i;
+        const uint32_t nbd = (uint32_t)bd.size();
         if (nbd == 0) continue;
         uint64_t items_words, meta_words;
         scratch_need(g, ctx->tune.bin_mode, tiles, &items_words, &meta_words);
@@ -525,7 +571,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             if (st) return st;
             {
                 ProfScope ps(ctx, SPD_K_BIN, s);
-                SPD_HIP(ctx, launch_bin(ctx->c, g, bd, nbd, tiles, ctx->items, ctx->meta, sp, s));
+                SPD_HIP(ctx, launch_bin(ctx->c, g, bd.data(), nbd, tiles, ctx->items, ctx->meta, sp, s));
             }
             {
                 ProfScope ps(ctx, SPD_K_TRANSPOSE, s);
@@ -548,9 +594,13 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                 hi[k] = as[k].tile_hi;
             }
             uint32_t *tot = ctx->aux, *base = ctx->aux + nsl * g.nb;
+            // the batch descriptors go to device memory through a pinned staging ring
+            BatchDesc *bdev = nullptr;
+            st = upload_batches(ctx, bd, s, &bdev);
+            if (st) return st;
             {
                 ProfScope ps(ctx, SPD_K_COUNT, s);
-                SPD_HIP(ctx, launch_count(ctx->c, g, bd, nbd, tiles, ctx->meta, s));
+                SPD_HIP(ctx, launch_count(ctx->c, g, bdev, nbd, tiles, ctx->meta, s));
             }
             {
                 ProfScope ps(ctx, SPD_K_OFFSETS, s);
@@ -561,7 +611,10 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             }
             {
                 ProfScope ps(ctx, SPD_K_BIN, s);
-                SPD_HIP(ctx, launch_place(ctx->c, g, bd, nbd, tiles, ctx->items, ctx->meta, ctx->metaB, sp, s));
+                SPD_HIP(ctx, launch_place(ctx->c, g, bdev, nbd, tiles, ctx->items, ctx->meta, ctx->metaB, sp, s));
+                // the staging slot may be rewritten once the placement kernel has read it
+                SPD_HIP(ctx, hipEventRecord(ctx->bd_ev[ctx->bd_next], s));
+                ctx->bd_next = (ctx->bd_next + 1) % kBdRing;
             }
             {
                 ProfScope ps(ctx, SPD_K_APPLY, s);
@@ -886,6 +939,9 @@ void spd_destroy(spd_ctx *ctx) {
         dev_free(ctx, &ctx->metaT, ctx->meta_words * 4);
         dev_free(ctx, &ctx->metaB, ctx->meta_words * 4);
         dev_free(ctx, &ctx->aux, ctx->aux_words * 4);
+        free_batch_ring(ctx);
+        for (auto &e : ctx->bd_ev)
+            if (e) (void)hipEventDestroy(e);
         close_buf_free(ctx, ctx->cbuf);
         dev_free(ctx, &ctx->view, ctx->view_words * 4);
         if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
@@ -1198,11 +1254,14 @@ struct spd_server {
     std::deque<SrvResult> done;
     std::vector<hipEvent_t> ev_pool;
     hipStream_t scan_s = nullptr, close_s = nullptr;
+    hipEvent_t scan_ev = nullptr; // recorded after each fused group on scan_s
+    bool scan_ev_set = false;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::thread worker;
     bool stop = false;
     uint32_t flushing = 0;        // drain calls in progress: scan every queued pair regardless of min_scan_pairs
+    uint32_t launching = 0;       // closes decided whose work is not yet in `closing` (their slot is in neither list)
     uint64_t queued = 0;          // batches submitted and not yet fully scanned
     spd_server_stats st{};
     spd_status fault = SPD_OK;    // first error seen by the scheduler
@@ -1299,7 +1358,10 @@ void srv_loop(spd_server *S) {
             for (auto &x : S->routers) open += x.slot >= 0;
             S->st.max_open = std::max(S->st.max_open, open);
         }
-        // ---- one fused group from the routers that hold a slot, round robin
+        // ---- one fused group from the routers that hold a slot, round robin.  While the scan
+        // stream is busy, a router's pairs wait until min_scan_pairs have gathered (each scan of a
+        // slot reads and writes all its buckets); when it is idle, whatever is queued is taken.
+        const bool idle = !S->scan_ev_set || hipEventQuery(S->scan_ev) == hipSuccess;
         std::vector<WorkItem> group;
         std::vector<SrvClose> closes;
         std::vector<uint64_t> finished_batches;
@@ -1308,9 +1370,7 @@ void srv_loop(spd_server *S) {
             const uint32_t ri = (S->rr + k) % R;
             SrvRouter &r = S->routers[ri];
             if (r.slot < 0 || r.q.empty()) continue;
-            // a router's queued pairs are scanned together once there are enough of them (each scan
-            // of a slot reads and writes all its buckets), or when its window can end now
-            const bool due = S->stop || S->flushing || r.close_pending || r.pending >= S->cfg.min_scan_pairs ||
+            const bool due = idle || S->stop || S->flushing || r.close_pending || r.pending >= S->cfg.min_scan_pairs ||
                              (S->cfg.window_pairs && r.in_window + r.pending >= S->cfg.window_pairs);
             if (!due) continue;
             while (!r.q.empty() && gp < S->cfg.max_group_pairs && group.size() < S->cfg.max_group_batches) {
@@ -1335,6 +1395,7 @@ void srv_loop(spd_server *S) {
                 }
                 if (close) {
                     closes.push_back(SrvClose{ri, r.slot, r.window, r.in_window, t});
+                    S->launching++;
                     r.slot = -1;
                     r.in_window = 0;
                     r.window++;
@@ -1345,20 +1406,33 @@ void srv_loop(spd_server *S) {
         S->rr = (S->rr + 1) % std::max<uint32_t>(1, R);
         if (group.empty() && closes.empty()) {
             if (S->stop && S->queued == 0 && S->closing.empty()) return;
+            // queued pairs of open windows that are not due yet: look again once the scan stream
+            // may have drained
+            bool deferred = false;
+            for (auto &r : S->routers) deferred = deferred || (r.slot >= 0 && !r.q.empty());
             if (!S->closing.empty()) {
                 lk.unlock();
-                srv_reap(S, true);
+                srv_reap(S, !deferred);
                 lk.lock();
+                if (deferred) S->cv_work.wait_for(lk, std::chrono::microseconds(50));
                 continue;
             }
-            S->cv_work.wait(lk);
+            if (deferred)
+                S->cv_work.wait_for(lk, std::chrono::microseconds(50));
+            else
+                S->cv_work.wait(lk);
             continue;
         }
         S->st.groups += group.empty() ? 0 : 1;
         lk.unlock();
         // ---- device work outside the lock
         spd_status st = SPD_OK;
-        if (!group.empty()) st = scan_work(S->ctx, group, S->scan_s);
+        if (!group.empty()) {
+            st = scan_work(S->ctx, group, S->scan_s);
+            if (!st && hipEventRecord(S->scan_ev, S->scan_s) != hipSuccess) st = SPD_E_HIP;
+            S->scan_ev_set = !st;
+        }
+        size_t pushed = 0;
         for (auto &c : closes) {
             if (st) break;
             hipEvent_t scanned = srv_event(S), fin = srv_event(S);
@@ -1382,6 +1456,12 @@ void srv_loop(spd_server *S) {
             std::lock_guard<std::mutex> g(S->mu);
             S->ev_pool.push_back(scanned);   // reusable once recorded again later (ordering kept by the stream)
             S->closing.push_back(SrvClosing{c.slot, c.router, c.window, c.pairs, c.t_req, fin});
+            S->launching--;
+            ++pushed;
+        }
+        if (pushed < closes.size()) {
+            std::lock_guard<std::mutex> g(S->mu);
+            S->launching -= (uint32_t)(closes.size() - pushed);
         }
         if (st) {
             srv_fault(S, st);
@@ -1409,7 +1489,7 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
     if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = 4ull << 30;
     if (!S->cfg.max_group_pairs) S->cfg.max_group_pairs = 64ull << 20;
     if (!S->cfg.min_scan_pairs) S->cfg.min_scan_pairs = std::max<uint64_t>(8ull << 20, S->cfg.window_pairs / 4);
-    if (!S->cfg.max_group_batches) S->cfg.max_group_batches = kMaxGroup;
+    if (!S->cfg.max_group_batches) S->cfg.max_group_batches = 1024;
     S->cfg.max_group_batches = std::min<uint32_t>(S->cfg.max_group_batches, 4096);
     spd_status st = ctx_create(p, 0, 0, S->cfg.hbm_budget_bytes, &S->ctx);
     if (st) {
@@ -1454,7 +1534,8 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
     S->st.slots = n_slots;
     S->routers.resize(S->cfg.n_routers);
     if (hipStreamCreateWithFlags(&S->scan_s, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&S->close_s, hipStreamNonBlocking) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipStreamCreateWithFlags(&S->close_s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S->scan_ev, hipEventDisableTiming) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         spd_server_destroy(S);
         return SPD_E_HIP;
     }
@@ -1527,7 +1608,7 @@ spd_status spd_server_drain(spd_server *S) {
     bool stuck = false;
     S->cv_done.wait(lk, [&] {
         if (S->fault) return true;
-        if (!S->closing.empty()) return false;
+        if (!S->closing.empty() || S->launching) return false;
         if (!S->queued) return true;   // a window without a close request simply stays open
         // every slot is held by an open window that will never close while the routers that
         // still have batches wait for one: no progress is possible
@@ -1583,6 +1664,7 @@ void spd_server_destroy(spd_server *S) {
         for (auto &cb : S->cbs) close_buf_free(S->ctx, cb);
         for (auto e : S->ev_pool) (void)hipEventDestroy(e);
         for (auto &c : S->closing) (void)hipEventDestroy(c.done);
+        if (S->scan_ev) (void)hipEventDestroy(S->scan_ev);
         if (S->scan_s) (void)hipStreamDestroy(S->scan_s);
         if (S->close_s) (void)hipStreamDestroy(S->close_s);
         spd_destroy(S->ctx);
