@@ -395,7 +395,8 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
 }
 
 // The bucket counts of bin_hash_pairs without keeping the items.  NEEDQ = false: a bucket holds
-// whole LDCs (at least k bits), so its index does not depend on H3.
+// whole LDCs (at least k bits) and a row holds more than one bucket, so a bucket index is the top
+// bits of LH_r alone (H3 is not needed).
 template <int LR, int PPT, int BLOCK, bool FULL, bool NEEDQ>
 __device__ __forceinline__ void count_hash_pairs(const Consts &c, const BinGeometry &g, const u32x2 (&pr)[PPT],
                                                  uint64_t p0, uint64_t n, uint32_t *hl, uint32_t *samp, uint32_t *misc) {
@@ -404,11 +405,19 @@ __device__ __forceinline__ void count_hash_pairs(const Consts &c, const BinGeome
     for (int j = 0; j < PPT; ++j) {
         if (!FULL && p0 + (uint64_t)j * BLOCK + tid >= n) continue;
         const uint32_t hip = pr[j].x, oip = pr[j].y;
-        const uint32_t q = NEEDQ ? ldc_bit(oip, c) : 0u;
+        if (NEEDQ) {
+            const uint32_t q = ldc_bit(oip, c);
 #pragma unroll
-        for (int r = 0; r < LR; ++r) {
-            uint32_t bit = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
-            atomicAdd(&hl[bit >> g.S], 1u);
+            for (int r = 0; r < LR; ++r) {
+                uint32_t bit = ldca_bit((uint32_t)r, ldc_col(hip, (uint32_t)r, c), q, c);
+                atomicAdd(&hl[bit >> g.S], 1u);
+            }
+        } else {
+            // bucket = (r * LC + col) >> (S - log2 k): the top nbits bits of LH_r, after r's rows
+            const uint32_t nbits = c.log2lc + c.log2k - g.S;   // >= 1 on this path
+#pragma unroll
+            for (int r = 0; r < LR; ++r)
+                atomicAdd(&hl[((uint32_t)r << nbits) + (mas_hi(hip, c.mul[3 + r], c.add[3 + r]) >> (32u - nbits))], 1u);
         }
         if (sampled(oip, c)) {   // staged; its SR items are counted by the whole workgroup later
             const uint32_t e = atomicAdd(&misc[0], 1u);
@@ -448,7 +457,7 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchL
     }
     __syncthreads();
     const bool full = p0 + (uint64_t)(PPT * BLOCK) <= B.n;
-    if (g.S < c.log2k) {
+    if (g.S < c.log2k || g.S >= c.log2lc + c.log2k) {
         if (full) count_hash_pairs<LR, PPT, BLOCK, true, true>(c, g, pr, p0, B.n, hl, samp, misc);
         else count_hash_pairs<LR, PPT, BLOCK, false, true>(c, g, pr, p0, B.n, hl, samp, misc);
     } else {
