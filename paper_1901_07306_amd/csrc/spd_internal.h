@@ -112,16 +112,32 @@ hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t
 hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
                       uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s);
 hipError_t launch_transpose(const uint32_t *meta, uint32_t *metaT, uint32_t rows, uint32_t cols, hipStream_t s);
+// Buffers the counting kernel zeroes on the way (the SEAVs of fresh slots); words a multiple of 4.
+struct ClearList {
+    uint32_t *p[kMaxGroup];
+    uint64_t words[kMaxGroup];
+    uint32_t n;
+};
+
 // Counting and placement of the bucket-major layout: batches_dev is a device array of n_batches
 // descriptors (any number), sorted by first_tile.
 hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
-                        uint32_t n_tiles, uint32_t *cnt, hipStream_t s);
-hipError_t launch_offsets(const uint32_t *cnt, uint32_t *cntT, uint32_t *offT, uint32_t *off, uint32_t *tot,
-                          uint32_t *base, const uint32_t *tile_lo, const uint32_t *tile_hi, uint32_t n_slots,
-                          uint32_t nb, uint32_t n_tiles, hipStream_t s);
+                        uint32_t n_tiles, uint32_t *cnt, const ClearList &clear, hipStream_t s);
+// Tiles of a bucket-major launch, per slot [lo, hi), scanned in chunks of kChunk tiles that never
+// span two slots: chunks cbase[s] .. cbase[s + 1] - 1 belong to slot s.
+constexpr uint32_t kChunk = 128;
+struct ChunkTable {
+    uint32_t lo[kMaxGroup], hi[kMaxGroup];
+    uint32_t cbase[kMaxGroup + 1];
+    uint32_t n;
+};
+// cnt [tiles][nb] -> loc [tiles][nb] (offset inside the tile's chunk), cstart [chunks][nb] (chunk
+// start, absolute), base [n * nb + 1] (start of each (slot, bucket), then the total).
+hipError_t launch_offsets(const uint32_t *cnt, uint32_t *loc, uint32_t *cstart, uint32_t *base, const ChunkTable &ct,
+                          uint32_t nb, hipStream_t s);
 hipError_t launch_place(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
-                        uint32_t n_tiles, uint32_t *items, const uint32_t *cnt, const uint32_t *off,
-                        const SlotPtrs *slots, hipStream_t s);
+                        uint32_t n_tiles, uint32_t *items, const uint32_t *cnt, const uint32_t *loc,
+                        const uint32_t *cstart, const ChunkTable &ct, const SlotPtrs *slots, hipStream_t s);
 struct ApplySlot {
     uint32_t *ldca;
     uint32_t *seav_w;

@@ -432,7 +432,8 @@ __device__ __forceinline__ void count_hash_pairs(const Consts &c, const BinGeome
 // Exact per-tile item counts by bucket (the first pass of the bucket-major layout): the same bit
 // addresses as k_bin, counted in LDS, SEAV items left out for tiles that record them directly.
 template <int LR, int PPT, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchList bl, uint32_t *__restrict__ cnt) {
+__global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchList bl, ClearList clr,
+                                                 uint32_t *__restrict__ cnt) {
     extern __shared__ uint32_t lds[];
     __shared__ RowLds rl;   // read after the first barrier
     rows_to_lds(rl, c);
@@ -454,6 +455,14 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchL
     for (int j = 0; j < PPT; ++j) {
         const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
         pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
+    }
+    // the SEAVs of fresh slots, spread over the whole grid (16-byte stores)
+    {
+        const uint64_t gt = (uint64_t)blockIdx.x * BLOCK + tid, stride = (uint64_t)gridDim.x * BLOCK;
+        for (uint32_t k = 0; k < clr.n; ++k) {
+            u32x4 *p4 = reinterpret_cast<u32x4 *>(clr.p[k]);
+            for (uint64_t w = gt; w < clr.words[k] / 4; w += stride) p4[w] = u32x4{0u, 0u, 0u, 0u};
+        }
     }
     __syncthreads();
     const bool full = p0 + (uint64_t)(PPT * BLOCK) <= B.n;
@@ -537,9 +546,9 @@ __device__ __forceinline__ void place_hash_pairs(const Consts &c, const RowLds &
 // items were left out of the counts (more sampled pairs than the stage reserves) records them with
 // global atomics instead, exactly as k_count decided.
 template <int LR, int PPT, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchList bl, SlotTable st,
+__global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchList bl, SlotTable st, ChunkTable ct,
                                                  uint64_t *__restrict__ items, const uint32_t *__restrict__ cnt,
-                                                 const uint32_t *__restrict__ off) {
+                                                 const uint32_t *__restrict__ off, const uint32_t *__restrict__ cstart) {
     extern __shared__ uint32_t lds[];
     __shared__ RowLds rl;   // read after the first barrier
     rows_to_lds(rl, c);
@@ -557,16 +566,19 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchL
 
     // counts and global offsets of this tile (two per thread held in registers), and the pairs:
     // every load is issued before the first wait
-    const uint32_t *ct = cnt + (uint64_t)tile * nb;
+    // this tile's offset of bucket b = its offset inside its chunk + the chunk's start
+    const uint32_t chunk = ct.cbase[B.slot] + (tile - ct.lo[B.slot]) / kChunk;
+    const uint32_t *ctr = cnt + (uint64_t)tile * nb;
     const uint32_t *ot = off + (uint64_t)tile * nb;
+    const uint32_t *cs0 = cstart + (uint64_t)chunk * nb;
     uint32_t c_pre[2] = {0u, 0u}, o_pre[2] = {0u, 0u};
     if (tid < nb) {
-        c_pre[0] = ct[tid];
-        o_pre[0] = ot[tid];
+        c_pre[0] = ctr[tid];
+        o_pre[0] = ot[tid] + cs0[tid];
     }
     if (tid + BLOCK < nb) {
-        c_pre[1] = ct[tid + BLOCK];
-        o_pre[1] = ot[tid + BLOCK];
+        c_pre[1] = ctr[tid + BLOCK];
+        o_pre[1] = ot[tid + BLOCK] + cs0[tid + BLOCK];
     }
     const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
     const uint64_t last = B.n - 1;
@@ -577,7 +589,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchL
         pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
     }
     for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
-        const uint32_t v = m == 0 ? c_pre[0] : m == 1 ? c_pre[1] : ct[b];
+        const uint32_t v = m == 0 ? c_pre[0] : m == 1 ? c_pre[1] : ctr[b];
         cur[b] = (v + 2) / 3 * 3;
         lb[b] = 0;
     }
@@ -624,7 +636,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchL
         const uint32_t e = cur[b], s0 = lb[b], pe = lb[b + 1];
         if (e > s0)
             for (uint32_t p = e; p < pe; ++p) stage[p] = stage[e - 1];
-        cur[b] = (m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : ot[b]) / 3 - s0 / 3;
+        cur[b] = (m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : ot[b] + cs0[b]) / 3 - s0 / 3;
     }
     __syncthreads();
     // one thread per stage word: the stage holds full bit addresses, so a word's first item names
@@ -640,25 +652,27 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchL
 
 template <int LR, int PPT, int BLOCK>
 static void launch_bin_t(int kind, const Consts &c, const BinGeometry &g, const BatchTable &bt, const BatchList &bl,
-                         const SlotTable &st, uint32_t n_tiles, uint32_t *items, uint32_t *meta, const uint32_t *off,
-                         hipStream_t s) {
+                         const SlotTable &st, const ClearList &clr, const ChunkTable &ct, const uint32_t *cstart,
+                         uint32_t n_tiles, uint32_t *items, uint32_t *meta, const uint32_t *off, hipStream_t s) {
     if (kind == 0)
         hipLaunchKernelGGL((k_bin<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bt, st, items, meta);
     else if (kind == 1)
-        hipLaunchKernelGGL((k_place<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bl, st,
-                           reinterpret_cast<uint64_t *>(items), meta, off);
+        hipLaunchKernelGGL((k_place<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), g.lds_bytes, s, c, g, bl, st, ct,
+                           reinterpret_cast<uint64_t *>(items), meta, off, cstart);
     else
         hipLaunchKernelGGL((k_count<LR, PPT, BLOCK>), dim3(n_tiles), dim3(BLOCK), (2 * g.nb + 1 + 2 * g.scap) * 4u, s, c,
-                           g, bl, meta);
+                           g, bl, clr, meta);
 }
 
 template <int LR>
 static hipError_t launch_bin_lr(int kind, const Consts &c, const BinGeometry &g, const BatchTable &bt,
-                                const BatchList &bl, const SlotTable &st, uint32_t n_tiles, uint32_t *items,
-                                uint32_t *meta, const uint32_t *off, hipStream_t s) {
+                                const BatchList &bl, const SlotTable &st, const ClearList &clr, const ChunkTable &ct,
+                                const uint32_t *cstart, uint32_t n_tiles, uint32_t *items, uint32_t *meta,
+                                const uint32_t *off, hipStream_t s) {
     const uint32_t ppt = g.tile_pairs / g.block;
 #define SPD_BIN_CASE(B, P) \
-    else if (g.block == B && ppt == P) launch_bin_t<LR, P, B>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
+    else if (g.block == B && ppt == P)                                                                             \
+        launch_bin_t<LR, P, B>(kind, c, g, bt, bl, st, clr, ct, cstart, n_tiles, items, meta, off, s);
     if (false) {
     }
     SPD_BIN_CASE(1024, 16) SPD_BIN_CASE(1024, 8) SPD_BIN_CASE(1024, 4) SPD_BIN_CASE(512, 16) SPD_BIN_CASE(512, 8)
@@ -672,7 +686,12 @@ static hipError_t launch_bin_lr(int kind, const Consts &c, const BinGeometry &g,
 // 2 = k_count (both: batches in device memory, any number)
 static hipError_t launch_bin_kind(int kind, const Consts &c, const BinGeometry &g, const BatchDesc *batches,
                                   uint32_t n_batches, uint32_t n_tiles, uint32_t *items, uint32_t *meta,
-                                  const uint32_t *off, const SlotPtrs *slots, hipStream_t s) {
+                                  const uint32_t *off, const SlotPtrs *slots, const ClearList *clear,
+                                  const ChunkTable *chunks, const uint32_t *cstart, hipStream_t s) {
+    ClearList clr{};
+    if (clear) clr = *clear;
+    ChunkTable ct{};
+    if (chunks) ct = *chunks;
     BatchTable bt{};
     BatchList bl{};
     SlotTable st{};
@@ -688,86 +707,113 @@ static hipError_t launch_bin_kind(int kind, const Consts &c, const BinGeometry &
     if (slots)
         for (int i = 0; i < kMaxGroup; ++i) st.s[i] = slots[i];
     switch (c.lr) {
-    case 1: return launch_bin_lr<1>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
-    case 2: return launch_bin_lr<2>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
-    case 3: return launch_bin_lr<3>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
-    case 4: return launch_bin_lr<4>(kind, c, g, bt, bl, st, n_tiles, items, meta, off, s);
+    case 1: return launch_bin_lr<1>(kind, c, g, bt, bl, st, clr, ct, cstart, n_tiles, items, meta, off, s);
+    case 2: return launch_bin_lr<2>(kind, c, g, bt, bl, st, clr, ct, cstart, n_tiles, items, meta, off, s);
+    case 3: return launch_bin_lr<3>(kind, c, g, bt, bl, st, clr, ct, cstart, n_tiles, items, meta, off, s);
+    case 4: return launch_bin_lr<4>(kind, c, g, bt, bl, st, clr, ct, cstart, n_tiles, items, meta, off, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
                       uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s) {
-    return launch_bin_kind(0, c, g, batches, n_batches, n_tiles, items, meta, nullptr, slots, s);
+    return launch_bin_kind(0, c, g, batches, n_batches, n_tiles, items, meta, nullptr, slots, nullptr, nullptr, nullptr, s);
 }
 
 hipError_t launch_place(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
-                        uint32_t n_tiles, uint32_t *items, const uint32_t *cnt, const uint32_t *off,
-                        const SlotPtrs *slots, hipStream_t s) {
-    return launch_bin_kind(1, c, g, batches_dev, n_batches, n_tiles, items, const_cast<uint32_t *>(cnt), off, slots, s);
+                        uint32_t n_tiles, uint32_t *items, const uint32_t *cnt, const uint32_t *loc,
+                        const uint32_t *cstart, const ChunkTable &ct, const SlotPtrs *slots, hipStream_t s) {
+    return launch_bin_kind(1, c, g, batches_dev, n_batches, n_tiles, items, const_cast<uint32_t *>(cnt), loc, slots,
+                           nullptr, &ct, cstart, s);
 }
 
 hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
-                        uint32_t n_tiles, uint32_t *cnt, hipStream_t s) {
-    return launch_bin_kind(2, c, g, batches_dev, n_batches, n_tiles, nullptr, cnt, nullptr, nullptr, s);
+                        uint32_t n_tiles, uint32_t *cnt, const ClearList &clear, hipStream_t s) {
+    return launch_bin_kind(2, c, g, batches_dev, n_batches, n_tiles, nullptr, cnt, nullptr, nullptr, &clear, nullptr,
+                           nullptr, s);
 }
 
 // ---- offsets of the bucket-major layout
-struct RangeTable {
-    uint32_t lo[kMaxGroup], hi[kMaxGroup];   // tile range of each slot of the launch
-    uint32_t n;
-};
-
-// One workgroup per (slot, bucket): exclusive prefix over the slot's tiles of the bucket's counts,
-// each rounded up to a multiple of 3 (whole 64-bit words).  offT[b][t] relative to the segment
-// start; tot[slot * nb + b] = the bucket's padded total.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_rowscan(const uint32_t *cntT, uint32_t *offT,
-                                                   uint32_t *__restrict__ tot, RangeTable rt, uint32_t nb,
-                                                   uint32_t n_tiles) {
-    __shared__ uint32_t wsum[BLOCK / 64 + 1];
-    const uint32_t si = blockIdx.x / nb, b = blockIdx.x % nb;
-    const uint32_t lo = rt.lo[si], hi = rt.hi[si];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
-    const uint32_t *row = cntT + (uint64_t)b * n_tiles;
-    uint32_t *orow = offT + (uint64_t)b * n_tiles;
-    uint32_t carry = 0;
-    for (uint32_t t0 = lo; t0 < hi; t0 += BLOCK) {
-        const uint32_t t = t0 + tid;
-        const uint32_t v = t < hi ? (row[t] + 2) / 3 * 3 : 0u;
-        uint32_t incl = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t x = __shfl_up(incl, o, 64);
-            if ((int)lane >= o) incl += x;
-        }
-        if (lane == 63u) wsum[wid] = incl;
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t run = 0;
-            for (uint32_t w = 0; w < BLOCK / 64; ++w) {
-                uint32_t x = wsum[w];
-                wsum[w] = run;
-                run += x;
-            }
-            wsum[BLOCK / 64] = run;
-        }
-        __syncthreads();
-        if (t < hi) orow[t] = carry + wsum[wid] + incl - v;
-        carry += wsum[BLOCK / 64];
-        __syncthreads();
-    }
-    if (tid == 0) tot[blockIdx.x] = carry;
+// Per slot, bucket b's items are the concatenation over the slot's tiles of each tile's segment
+// (count rounded up to a multiple of 3: whole 64-bit words); slots follow each other per bucket:
+// base[s * nb + b] = start of (slot s, bucket b).  Tiles are scanned in chunks of kChunk that
+// never span two slots: k_colscan writes each (tile, bucket) offset inside its chunk and each
+// chunk's total, k_chunkscan turns the chunk totals into chunk starts (base included), and
+// k_place adds a tile's chunk start to its offsets.
+__device__ __forceinline__ uint32_t slot_of_chunk(const ChunkTable &ct, uint32_t c) {
+    uint32_t si = 0;
+    while (si + 1 < ct.n && ct.cbase[si + 1] <= c) ++si;
+    return si;
 }
 
-// Exclusive prefix of the padded bucket totals: base[g], base[n] = all items.
-__global__ __launch_bounds__(1024) void k_basescan(const uint32_t *__restrict__ tot, uint32_t *__restrict__ base,
-                                                   uint32_t n) {
+// grid (ceil(nb / 64), chunks), 256 threads: 64 buckets x 4 groups of 32 tiles
+__global__ __launch_bounds__(256) void k_colscan(const uint32_t *__restrict__ cnt, uint32_t *__restrict__ loc,
+                                                 uint32_t *__restrict__ csum, ChunkTable ct, uint32_t nb) {
+    static_assert(kChunk == 128, "four groups of 32 tiles");
+    __shared__ uint32_t ps[4][64];
+    const uint32_t c = blockIdx.y;
+    const uint32_t si = slot_of_chunk(ct, c);
+    const uint32_t t0 = ct.lo[si] + (c - ct.cbase[si]) * kChunk;
+    const uint32_t t1 = t0 + kChunk < ct.hi[si] ? t0 + kChunk : ct.hi[si];   // > t0
+    const uint32_t col = threadIdx.x & 63u, rg = threadIdx.x >> 6;
+    const uint32_t b = blockIdx.x * 64 + col;
+    const bool okb = b < nb;
+    const uint32_t bb = okb ? b : nb - 1;
+    const uint32_t r0 = t0 + rg * 32;
+    uint32_t v[32];
+#pragma unroll
+    for (uint32_t k = 0; k < 32; ++k) {   // unconditional (clamped) loads, all in flight together
+        const uint32_t t = r0 + k < t1 ? r0 + k : t1 - 1;
+        v[k] = cnt[(uint64_t)t * nb + bb];
+    }
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 32; ++k) {
+        const uint32_t x = (r0 + k < t1) ? (v[k] + 2) / 3 * 3 : 0u;
+        v[k] = sum;
+        sum += x;
+    }
+    ps[rg][col] = sum;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (uint32_t r = 0; r < rg; ++r) pre += ps[r][col];
+    if (okb) {
+#pragma unroll
+        for (uint32_t k = 0; k < 32; ++k)
+            if (r0 + k < t1) loc[(uint64_t)(r0 + k) * nb + b] = pre + v[k];
+        if (rg == 3) csum[(uint64_t)c * nb + b] = pre + sum;
+    }
+}
+
+// One workgroup: chunk totals -> chunk starts (in place, base included); base[s * nb + b] and
+// base[n * nb] = all items.
+__global__ __launch_bounds__(1024) void k_chunkscan(uint32_t *__restrict__ csum, uint32_t *__restrict__ base,
+                                                    ChunkTable ct, uint32_t nb) {
     __shared__ uint32_t wsum[17];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+    const uint32_t n = ct.n * nb;
+    // 1. per (slot, bucket): exclusive prefix over the slot's chunks; the total goes to base
+    for (uint32_t e = tid; e < n; e += 1024) {
+        const uint32_t s = e / nb, b = e - s * nb;
+        uint32_t run = 0;
+        for (uint32_t c0 = ct.cbase[s]; c0 < ct.cbase[s + 1]; c0 += 8) {
+            uint32_t x[8];
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) x[k] = c0 + k < ct.cbase[s + 1] ? csum[(uint64_t)(c0 + k) * nb + b] : 0u;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) {
+                if (c0 + k < ct.cbase[s + 1]) csum[(uint64_t)(c0 + k) * nb + b] = run;
+                run += x[k];
+            }
+        }
+        base[e] = run;
+    }
+    __syncthreads();
+    // 2. exclusive prefix of the (slot, bucket) totals
     uint32_t carry = 0;
     for (uint32_t i0 = 0; i0 < n; i0 += 1024) {
         const uint32_t i = i0 + tid;
-        const uint32_t v = i < n ? tot[i] : 0u;
+        const uint32_t v = i < n ? base[i] : 0u;
         uint32_t incl = v;
         for (int o = 1; o < 64; o <<= 1) {
             uint32_t x = __shfl_up(incl, o, 64);
@@ -790,46 +836,20 @@ __global__ __launch_bounds__(1024) void k_basescan(const uint32_t *__restrict__ 
         __syncthreads();
     }
     if (tid == 0) base[n] = carry;
-}
-
-// off[t][b] = base[slot(t) * nb + b] + offT[b][t]
-__global__ __launch_bounds__(256) void k_offsets(const uint32_t *__restrict__ offT, const uint32_t *__restrict__ base,
-                                                 uint32_t *__restrict__ off, RangeTable rt, uint32_t nb,
-                                                 uint32_t n_tiles) {
-    __shared__ uint32_t t[32][33];
-    const uint32_t bx = blockIdx.y * 32, by = blockIdx.x * 32;   // bx: bucket block, by: tile block
-    const uint32_t tx = threadIdx.x & 31u, ty = threadIdx.x >> 5;
-    for (uint32_t k = ty; k < 32; k += 8) {
-        uint32_t b = bx + k, tile = by + tx;
-        if (b < nb && tile < n_tiles) t[k][tx] = offT[(uint64_t)b * n_tiles + tile];
-    }
     __syncthreads();
-    for (uint32_t k = ty; k < 32; k += 8) {
-        uint32_t tile = by + k, b = bx + tx;
-        if (b < nb && tile < n_tiles) {
-            uint32_t si = 0;
-            while (si + 1 < rt.n && rt.lo[si + 1] <= tile) ++si;
-            off[(uint64_t)tile * nb + b] = base[si * nb + b] + t[tx][k];
-        }
+    // 3. chunk starts become absolute
+    for (uint32_t e = tid; e < n; e += 1024) {
+        const uint32_t s = e / nb, b = e - s * nb, add = base[e];
+        for (uint32_t c = ct.cbase[s]; c < ct.cbase[s + 1]; ++c) csum[(uint64_t)c * nb + b] += add;
     }
 }
 
-hipError_t launch_offsets(const uint32_t *cnt, uint32_t *cntT, uint32_t *offT, uint32_t *off, uint32_t *tot,
-                          uint32_t *base, const uint32_t *tile_lo, const uint32_t *tile_hi, uint32_t n_slots,
-                          uint32_t nb, uint32_t n_tiles, hipStream_t s) {
-    RangeTable rt{};
-    if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup || (nb + 31) / 32 > 65535u) return hipErrorInvalidValue;
-    for (uint32_t i = 0; i < n_slots; ++i) {
-        rt.lo[i] = tile_lo[i];
-        rt.hi[i] = tile_hi[i];
-    }
-    rt.n = n_slots;
-    hipError_t e = launch_transpose(cnt, cntT, n_tiles, nb, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rowscan<1024>, dim3(n_slots * nb), dim3(1024), 0, s, cntT, offT, tot, rt, nb, n_tiles);
-    hipLaunchKernelGGL(k_basescan, dim3(1), dim3(1024), 0, s, tot, base, n_slots * nb);
-    dim3 grid((n_tiles + 31) / 32, (nb + 31) / 32);
-    hipLaunchKernelGGL(k_offsets, grid, dim3(256), 0, s, offT, base, off, rt, nb, n_tiles);
+hipError_t launch_offsets(const uint32_t *cnt, uint32_t *loc, uint32_t *csum, uint32_t *base, const ChunkTable &ct,
+                          uint32_t nb, hipStream_t s) {
+    if (ct.n == 0 || ct.n > (uint32_t)kMaxGroup || ct.cbase[ct.n] == 0 || ct.cbase[ct.n] > 65535u)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_colscan, dim3((nb + 63) / 64, ct.cbase[ct.n]), dim3(256), 0, s, cnt, loc, csum, ct, nb);
+    hipLaunchKernelGGL(k_chunkscan, dim3(1), dim3(1024), 0, s, csum, base, ct, nb);
     return hipGetLastError();
 }
 

@@ -37,11 +37,13 @@ constexpr uint32_t kRecChunk = 4096;   // records copied back together with the 
 
 // Device and pinned host buffers of one end-of-window pass.
 struct CloseBuf {
-    uint32_t *rec = nullptr;          // device (ip, z0) records
+    // one device buffer: 4 counters ([0] reported, [1] candidates) then the (ip, z0) records, so that
+    // the counters and the first kRecChunk records come back in one copy
+    uint32_t *counters = nullptr;
+    uint32_t *rec = nullptr;          // counters + 4
     uint32_t rec_cap = 0;
-    uint32_t *counters = nullptr;     // device [0] reported, [1] candidates
-    uint32_t *h_counters = nullptr;   // pinned
-    uint32_t *h_rec = nullptr;        // pinned
+    uint32_t *h_counters = nullptr;   // pinned, same layout, kRecChunk records
+    uint32_t *h_rec = nullptr;        // pinned, all records when there are more than kRecChunk
     uint32_t h_rec_cap = 0;
     bool empty = false;               // the slot was fresh: nothing was launched
     hipGraphExec_t graph = nullptr;   // captured close of graph_slot
@@ -509,9 +511,11 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
     BinGeometry g{};
     const bool binned = total > ctx->tune.direct_max_pairs && ctx->p.lr <= 4 && bin_geometry(ctx, &g);
     std::vector<Slot *> fresh_slots;
+    const bool bm = ctx->tune.bin_mode != 0;
     for (Slot *sl : slots) {
         if (!sl->fresh) continue;
-        spd_status st = binned ? clear_seav(ctx, *sl, s) : clear_slot(ctx, *sl, s);
+        // bucket-major: the counting kernel clears a fresh slot's SEAV (before any bit reaches it)
+        spd_status st = !binned ? clear_slot(ctx, *sl, s) : bm ? SPD_OK : clear_seav(ctx, *sl, s);
         if (st) return st;
         if (binned) fresh_slots.push_back(sl);
         sl->fresh = false;
@@ -529,7 +533,6 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
     // take at most kMaxGroup batches per group, the bucket-major layout any number (its counting and
     // placement kernels run over the group in chunks of kMaxGroup batches, its offsets and apply
     // once per group, so each slot's buckets are read and written once per group)
-    const bool bm = ctx->tune.bin_mode != 0;
     size_t i0 = 0;
     while (i0 < ws.size()) {
         std::vector<BatchDesc> bd;
@@ -585,33 +588,41 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
         } else {
             if ((uint64_t)tiles * g.cap >= (1ull << 32))
                 return fail(ctx, SPD_E_INVALID, "launch too large for 32-bit item offsets");
-            spd_status st = ensure_scratch(ctx, items_words, meta_words, s);
-            if (!st) st = ensure_aux(ctx, 2ull * nsl * g.nb + 2, s);
-            if (st) return st;
-            uint32_t lo[kMaxGroup], hi[kMaxGroup];
+            // chunks of kChunk tiles, per slot
+            ChunkTable ct{};
+            ct.n = nsl;
             for (uint32_t k = 0; k < nsl; ++k) {
-                lo[k] = as[k].tile_lo;
-                hi[k] = as[k].tile_hi;
+                ct.lo[k] = as[k].tile_lo;
+                ct.hi[k] = as[k].tile_hi;
+                ct.cbase[k + 1] = ct.cbase[k] + (as[k].tile_hi - as[k].tile_lo + kChunk - 1) / kChunk;
             }
-            uint32_t *tot = ctx->aux, *base = ctx->aux + nsl * g.nb;
+            const uint32_t chunks = ct.cbase[nsl];
+            spd_status st = ensure_scratch(ctx, items_words, meta_words, s);
+            if (!st) st = ensure_aux(ctx, (uint64_t)nsl * g.nb + 1 + (uint64_t)chunks * g.nb, s);
+            if (st) return st;
+            uint32_t *base = ctx->aux, *cstart = ctx->aux + nsl * g.nb + 1;
             // the batch descriptors go to device memory through a pinned staging ring
             BatchDesc *bdev = nullptr;
             st = upload_batches(ctx, bd, s, &bdev);
             if (st) return st;
+            ClearList cl{};
+            for (uint32_t k = 0; k < nsl; ++k)
+                if (as[k].fresh) {
+                    cl.p[cl.n] = as[k].seav_w;
+                    cl.words[cl.n++] = ctx->seav_alloc / 4;
+                }
             {
                 ProfScope ps(ctx, SPD_K_COUNT, s);
-                SPD_HIP(ctx, launch_count(ctx->c, g, bdev, nbd, tiles, ctx->meta, s));
+                SPD_HIP(ctx, launch_count(ctx->c, g, bdev, nbd, tiles, ctx->meta, cl, s));
             }
             {
                 ProfScope ps(ctx, SPD_K_OFFSETS, s);
-                // counts stay in meta for k_place; the relative offsets are scanned in place in
-                // metaT; the global offsets go to metaB
-                SPD_HIP(ctx, launch_offsets(ctx->meta, ctx->metaT, ctx->metaT, ctx->metaB, tot, base, lo, hi, nsl, g.nb,
-                                            tiles, s));
+                // counts stay in meta for k_place; offsets inside each chunk go to metaB
+                SPD_HIP(ctx, launch_offsets(ctx->meta, ctx->metaB, cstart, base, ct, g.nb, s));
             }
             {
                 ProfScope ps(ctx, SPD_K_BIN, s);
-                SPD_HIP(ctx, launch_place(ctx->c, g, bdev, nbd, tiles, ctx->items, ctx->meta, ctx->metaB, sp, s));
+                SPD_HIP(ctx, launch_place(ctx->c, g, bdev, nbd, tiles, ctx->items, ctx->meta, ctx->metaB, cstart, ct, sp, s));
                 // the staging slot may be rewritten once the placement kernel has read it
                 SPD_HIP(ctx, hipEventRecord(ctx->bd_ev[ctx->bd_next], s));
                 ctx->bd_next = (ctx->bd_next + 1) % kBdRing;
@@ -631,29 +642,31 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------ end of window
+spd_status close_rec_alloc(spd_ctx *ctx, CloseBuf &cb, uint32_t cap) {
+    dev_free(ctx, &cb.counters, 16 + (uint64_t)cb.rec_cap * 8);
+    cb.rec = nullptr;
+    cb.rec_cap = 0;
+    spd_status st = dev_alloc(ctx, &cb.counters, 16 + (uint64_t)cap * 8);
+    if (st) return st;
+    cb.rec = cb.counters + 4;
+    cb.rec_cap = cap;
+    return SPD_OK;
+}
+
 spd_status close_buf_init(spd_ctx *ctx, CloseBuf &cb) {
     if (!cb.counters) {
-        spd_status st = dev_alloc(ctx, &cb.counters, 16);
+        spd_status st = close_rec_alloc(ctx, cb, kRecInit);
         if (st) return st;
     }
-    if (!cb.rec) {
-        spd_status st = dev_alloc(ctx, &cb.rec, (uint64_t)kRecInit * 8);
-        if (st) return st;
-        cb.rec_cap = kRecInit;
-    }
-    if (!cb.h_counters) SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_counters, 16, hipHostMallocDefault));
-    if (!cb.h_rec) {
-        SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_rec, (uint64_t)kRecChunk * 8, hipHostMallocDefault));
-        cb.h_rec_cap = kRecChunk;
-    }
+    if (!cb.h_counters) SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_counters, 16 + (uint64_t)kRecChunk * 8, hipHostMallocDefault));
     return SPD_OK;
 }
 
 void close_buf_free(spd_ctx *ctx, CloseBuf &cb) {
     if (cb.graph) (void)hipGraphExecDestroy(cb.graph);
     cb.graph = nullptr;
-    dev_free(ctx, &cb.rec, (uint64_t)cb.rec_cap * 8);
-    dev_free(ctx, &cb.counters, 16);
+    dev_free(ctx, &cb.counters, 16 + (uint64_t)cb.rec_cap * 8);
+    cb.rec = nullptr;
     if (cb.h_counters) (void)hipHostFree(cb.h_counters);
     if (cb.h_rec) (void)hipHostFree(cb.h_rec);
     cb.h_counters = nullptr;
@@ -709,8 +722,8 @@ spd_status close_launch_ops(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStrea
         ProfScope ps(ctx, SPD_K_CLOSE, s);
         SPD_HIP(ctx, launch_close(ctx->c, a, ctx->sliding, block, grid, s));
     }
-    SPD_HIP(ctx, hipMemcpyAsync(cb.h_counters, cb.counters, 16, hipMemcpyDeviceToHost, s));
-    SPD_HIP(ctx, hipMemcpyAsync(cb.h_rec, cb.rec, (uint64_t)std::min(cb.rec_cap, kRecChunk) * 8, hipMemcpyDeviceToHost, s));
+    SPD_HIP(ctx, hipMemcpyAsync(cb.h_counters, cb.counters, 16 + (uint64_t)std::min(cb.rec_cap, kRecChunk) * 8,
+                                hipMemcpyDeviceToHost, s));
     return SPD_OK;
 }
 
@@ -768,12 +781,8 @@ spd_status close_finish(spd_ctx *ctx, Slot &sl, CloseBuf &cb, hipStream_t s, std
     uint32_t n = cb.h_counters[0];
     ctx->stats.candidates_last = cb.h_counters[1];
     if (n > cb.rec_cap) {
-        dev_free(ctx, &cb.rec, (uint64_t)cb.rec_cap * 8);
-        cb.rec_cap = 0;
-        const uint32_t want = n + 1024;
-        spd_status st = dev_alloc(ctx, &cb.rec, (uint64_t)want * 8);
+        spd_status st = close_rec_alloc(ctx, cb, n + 1024);
         if (st) return st;
-        cb.rec_cap = want;
         st = close_launch_ops(ctx, sl, cb, s);
         if (st) return st;
         SPD_HIP(ctx, hipStreamSynchronize(s));
@@ -792,9 +801,10 @@ spd_status close_finish(spd_ctx *ctx, Slot &sl, CloseBuf &cb, hipStream_t s, std
     }
     out->resize(n);
     const uint32_t kmax = 1u << ctx->p.log2k;
+    const uint32_t *hr = n > kRecChunk ? cb.h_rec : cb.h_counters + 4;
     for (uint32_t i = 0; i < n; ++i) {
-        const uint32_t z0 = cb.h_rec[2 * i + 1];
-        (*out)[i] = spd_superpoint{cb.h_rec[2 * i], z0, ctx->est[std::min(z0, kmax)], z0 == 0 ? 1u : 0u};
+        const uint32_t z0 = hr[2 * i + 1];
+        (*out)[i] = spd_superpoint{hr[2 * i], z0, ctx->est[std::min(z0, kmax)], z0 == 0 ? 1u : 0u};
     }
     std::sort(out->begin(), out->end(), [](const spd_superpoint &x, const spd_superpoint &y) { return x.ip < y.ip; });
     ctx->stats.reported_last = n;
@@ -1505,7 +1515,8 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
         uint64_t items_words, meta_words;
         scratch_need(g, ctx->tune.bin_mode, tiles, &items_words, &meta_words);
         st = ensure_scratch(ctx, items_words, meta_words, nullptr);
-        if (!st && ctx->tune.bin_mode) st = ensure_aux(ctx, 2ull * kMaxGroup * g.nb + 2, nullptr);
+        if (!st && ctx->tune.bin_mode)
+            st = ensure_aux(ctx, (uint64_t)kMaxGroup * g.nb + 1 + (tiles / kChunk + kMaxGroup) * g.nb, nullptr);
         if (st) {
             spd_server_destroy(S);
             return st;
