@@ -111,6 +111,24 @@ def run_detector(spd, torch, params, x, steps, warmup, tune):
     return elapsed, close_ms, window_ms, breakdown, (dom, timed), rec, stats
 
 
+def run_both_directions(spd, torch, params, x, steps, warmup):
+    """Source- and destination-keyed super points of the same window: one fused scan call with the
+    pairs as given (router 0) and swapped (router 1), then both ends of window.  Returns pairs/s
+    (each pair counted once) and the two report sizes."""
+    det = spd.Detector(params, n_routers=2)
+    rep = None
+    for i in range(warmup + steps):
+        if i == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        det.scan_batches([(0, x), (1, x, spd.BATCH_DST)])
+        rep = (det.close_window(0), det.close_window(1))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    det.close()
+    return x.shape[0] * steps / el, el / steps * 1e3, [int(len(r)) for r in rep]
+
+
 def bench_serving(spd, torch, np, st, capacity_pps, windows_per_router, load, log_fn):
     """The serving loop on the 16-router workload: batches of log-uniform size in [4Ki, 4Mi] pairs,
     Poisson arrivals at `load` x capacity_pps, a window closed every 64Mi pairs per router.  Router
@@ -293,6 +311,12 @@ def main() -> int:
         "batched_over_plain": value / plain_value,
         "gpu": torch.cuda.get_device_name(0),
     }
+
+    log("both directions: one fused call, source- and destination-keyed")
+    bpps, bms, bsizes = run_both_directions(spd, torch, params, x, args.plain_steps, 1)
+    out["both_directions"] = {"value": bpps, "unit": "packets/s", "ms_per_step": bms,
+                              "reported_super_points": {"source_keyed": bsizes[0], "destination_keyed": bsizes[1]},
+                              "step": "scan of the window keyed both ways in one call + both ends of window"}
 
     if args.serving_windows > 0:
         log("serving loop: 16 routers")

@@ -84,9 +84,13 @@ typedef struct spd_superpoint {
 } spd_superpoint;
 
 /* One batch of a fused multi-router scan. */
+#define SPD_BATCH_DST 1u      /* spd_batch.flags: destination-keyed, each record read as (oip, hip) */
 typedef struct spd_batch {
     uint32_t router;           /* router (watch point) id, 0..n_routers-1 */
-    uint32_t reserved;         /* must be 0 */
+    uint32_t flags;            /* 0: source-keyed (element 0 is the monitored host); SPD_BATCH_DST:
+                                  destination-keyed, the super points of the opposite direction.
+                                  Both directions of one stream: give each its own router id and
+                                  the same pairs twice in one call (one fused launch). */
     const uint32_t *pairs_dev; /* device pointer to n_pairs (hip, oip) records */
     uint64_t n_pairs;
 } spd_batch;
@@ -225,6 +229,8 @@ const char *spd_last_error(const spd_ctx *ctx);
 typedef struct spd_server spd_server;
 
 #define SPD_SUBMIT_CLOSE 1u    /* close the router's window after this batch */
+#define SPD_SUBMIT_DST 2u      /* destination-keyed batch (records read as (oip, hip)); a router's
+                                  batches should all be keyed the same way */
 
 typedef struct spd_server_config {
     uint32_t n_routers;
@@ -276,7 +282,7 @@ spd_status spd_server_next(spd_server *srv, spd_window_result *hdr, spd_superpoi
 typedef struct spd_arrival {
     double t_s;                    /* arrival time in seconds from the start of the replay */
     uint32_t router;
-    uint32_t flags;                /* SPD_SUBMIT_CLOSE or 0 */
+    uint32_t flags;                /* SPD_SUBMIT_CLOSE and/or SPD_SUBMIT_DST, or 0 */
     const uint32_t *pairs_dev;
     uint64_t n_pairs;
 } spd_arrival;

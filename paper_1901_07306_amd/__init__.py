@@ -44,7 +44,7 @@ class SpdSuperpoint(ctypes.Structure):
 
 
 class SpdBatch(ctypes.Structure):
-    _fields_ = [("router", u32), ("reserved", u32), ("pairs_dev", ctypes.c_void_p), ("n_pairs", u64)]
+    _fields_ = [("router", u32), ("flags", u32), ("pairs_dev", ctypes.c_void_p), ("n_pairs", u64)]
 
 
 class SpdTuning(ctypes.Structure):
@@ -96,6 +96,7 @@ EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_bat
 
 SPD_E_AGAIN = -6
 SPD_SUBMIT_CLOSE = 1
+SPD_SUBMIT_DST = 2
 
 
 class SpdError(RuntimeError):
@@ -245,11 +246,17 @@ def spd_scan(ctx: int, router: int, pairs, stream=None) -> None:
     _check(lib().spd_scan(ctx, router, ptr or None, n, _stream_ptr(stream)), ctx)
 
 
-def spd_scan_batches(ctx: int, batches: Iterable[Tuple[int, "object"]], stream=None) -> None:
+BATCH_DST = 1   # destination-keyed batch: records read as (oip, hip)
+
+
+def spd_scan_batches(ctx: int, batches: Iterable[Tuple], stream=None) -> None:
+    """batches: (router, pairs) or (router, pairs, flags) with flags BATCH_DST for destination-keyed."""
     items = []
-    for router, pairs in batches:
+    for b in batches:
+        router, pairs = b[0], b[1]
+        flags = b[2] if len(b) > 2 else 0
         ptr, n = _pairs_ptr(pairs)
-        items.append(SpdBatch(router, 0, ptr or None, n))
+        items.append(SpdBatch(router, flags, ptr or None, n))
     arr = (SpdBatch * max(1, len(items)))(*items)
     _check(lib().spd_scan_batches(ctx, arr, len(items), _stream_ptr(stream)), ctx)
 
@@ -423,11 +430,12 @@ class Server:
         if st != SPD_OK:
             raise SpdError(st, lib().spd_server_last_error(self.h).decode() or lib().spd_strerror(st).decode())
 
-    def submit(self, router: int, pairs, close: bool = False, keep: bool = True):
+    def submit(self, router: int, pairs, close: bool = False, keep: bool = True, dst: bool = False):
         ptr, n = _pairs_ptr(pairs)
         if keep:
             self._keep.append(pairs)
-        self._check(lib().spd_server_submit(self.h, router, ptr or None, n, SPD_SUBMIT_CLOSE if close else 0))
+        flags = (SPD_SUBMIT_CLOSE if close else 0) | (SPD_SUBMIT_DST if dst else 0)
+        self._check(lib().spd_server_submit(self.h, router, ptr or None, n, flags))
 
     def next(self, timeout_ms: int = -1, cap: int = 1 << 16):
         """(header dict, structured array of super points) or None on timeout."""

@@ -90,6 +90,8 @@ struct BatchDesc {
     uint64_t n;
     uint32_t first_tile;
     uint32_t slot;       // index into the launch's slot table
+    uint32_t swap;       // 1: destination-keyed (each record read as (oip, hip))
+    uint32_t pad;
 };
 
 struct BinGeometry {

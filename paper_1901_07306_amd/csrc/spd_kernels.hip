@@ -17,6 +17,10 @@
 namespace spd {
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// A pair as the method sees it: (hip, oip) = the record, or the swapped record for a
+// destination-keyed batch (uniform per batch).
+__device__ __forceinline__ u32x2 keyed(u32x2 pr, uint32_t swap) { return swap ? u32x2{pr.y, pr.x} : pr; }
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct BatchTable {
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(1024) void k_scan_direct(Consts c, BatchTable bt, S
         uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
         const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
         for (uint64_t i = gtid; i < B.n; i += stride) {
-            u32x2 pr = __builtin_nontemporal_load(pairs + i);
+            const u32x2 pr = keyed(__builtin_nontemporal_load(pairs + i), B.swap);
             const uint32_t hip = pr.x, oip = pr.y;
             const uint32_t q = ldc_bit(oip, c);
             for (uint32_t r = 0; r < c.lr; ++r) {
@@ -185,7 +189,7 @@ __global__ __launch_bounds__(1024) void k_scan_stamp(Consts c, BatchTable bt, Sl
         const SlotPtrs S = st.s[B.slot];
         const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
         for (uint64_t i = gtid; i < B.n; i += stride) {
-            u32x2 pr = __builtin_nontemporal_load(pairs + i);
+            const u32x2 pr = keyed(__builtin_nontemporal_load(pairs + i), B.swap);
             const uint32_t hip = pr.x, oip = pr.y;
             const uint32_t q = ldc_bit(oip, c);
             for (uint32_t r = 0; r < c.lr; ++r) S.ldca_ts[ldca_bit(r, ldc_col(hip, r, c), q, c)] = v;
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
-        pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
+        pr[j] = keyed(__builtin_nontemporal_load(pairs + (idx < B.n ? idx : last)), B.swap);
     }
     __syncthreads();
 
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchL
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
-        pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
+        pr[j] = keyed(__builtin_nontemporal_load(pairs + (idx < B.n ? idx : last)), B.swap);
     }
     // the SEAVs of fresh slots, spread over the whole grid (16-byte stores)
     {
@@ -586,7 +590,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchL
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
-        pr[j] = __builtin_nontemporal_load(pairs + (idx < B.n ? idx : last));
+        pr[j] = keyed(__builtin_nontemporal_load(pairs + (idx < B.n ? idx : last)), B.swap);
     }
     for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
         const uint32_t v = m == 0 ? c_pre[0] : m == 1 ? c_pre[1] : ctr[b];

@@ -30,6 +30,7 @@ struct WorkItem {
     Slot *slot;
     const uint32_t *pairs;
     uint64_t n;
+    uint32_t swap = 0;   // destination-keyed batch
 };
 
 constexpr uint32_t kRecInit = 65536;   // device records per close buffer, grown on demand
@@ -397,12 +398,12 @@ void free_batch_ring(spd_ctx *ctx) {
 // Copy a launch's batch descriptors to device memory (next slot of the staging ring; the slot's
 // event, recorded after the kernels that read it, guards its reuse).  The caller records
 // bd_ev[bd_next] after its last kernel and advances bd_next.
-spd_status upload_batches(spd_ctx *ctx, const std::vector<BatchDesc> &bd, hipStream_t s, BatchDesc **out) {
+spd_status ensure_batch_ring(spd_ctx *ctx, size_t n) {
     for (uint32_t k = 0; k < kBdRing; ++k)
         if (!ctx->bd_ev[k]) SPD_HIP(ctx, hipEventCreateWithFlags(&ctx->bd_ev[k], hipEventDisableTiming));
-    if (bd.size() > ctx->bd_cap) {
+    if (n > ctx->bd_cap) {
         free_batch_ring(ctx);
-        const uint32_t cap = (uint32_t)std::max<size_t>(1024, (bd.size() + 1023) / 1024 * 1024);
+        const uint32_t cap = (uint32_t)std::max<size_t>(1024, (n + 1023) / 1024 * 1024);
         for (uint32_t k = 0; k < kBdRing; ++k) {
             SPD_HIP(ctx, hipHostMalloc((void **)&ctx->bd_host[k], cap * sizeof(BatchDesc), hipHostMallocDefault));
             spd_status st = dev_alloc(ctx, &ctx->bd_dev[k], (uint64_t)cap * sizeof(BatchDesc));
@@ -410,6 +411,12 @@ spd_status upload_batches(spd_ctx *ctx, const std::vector<BatchDesc> &bd, hipStr
         }
         ctx->bd_cap = cap;
     }
+    return SPD_OK;
+}
+
+spd_status upload_batches(spd_ctx *ctx, const std::vector<BatchDesc> &bd, hipStream_t s, BatchDesc **out) {
+    spd_status st = ensure_batch_ring(ctx, bd.size());
+    if (st) return st;
     const uint32_t k = ctx->bd_next;
     SPD_HIP(ctx, hipEventSynchronize(ctx->bd_ev[k]));
     std::memcpy(ctx->bd_host[k], bd.data(), bd.size() * sizeof(BatchDesc));
@@ -487,7 +494,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                     seen.push_back(ws[i].slot);
                     sp[nsl++] = ptrs_of(*ws[i].slot);
                 }
-                bd[nbd++] = BatchDesc{ws[i].pairs, ws[i].n, 0, si};
+                bd[nbd++] = BatchDesc{ws[i].pairs, ws[i].n, 0, si, ws[i].swap, 0};
                 n = std::max(n, ws[i].n);
             }
             uint32_t block = ctx->tune.direct_block;
@@ -526,7 +533,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
     if (lp) {
         std::vector<WorkItem> split;
         for (auto &w : ws)
-            for (uint64_t a = 0; a < w.n; a += lp) split.push_back(WorkItem{w.slot, w.pairs + 2 * a, std::min(lp, w.n - a)});
+            for (uint64_t a = 0; a < w.n; a += lp) split.push_back(WorkItem{w.slot, w.pairs + 2 * a, std::min(lp, w.n - a), w.swap});
         ws.swap(split);
     }
     // binned: launch groups of at most kMaxGroup slots and launch_pairs pairs; per-tile regions also
@@ -560,7 +567,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             }
             const uint64_t nt = (w.n + g.tile_pairs - 1) / g.tile_pairs;
             if ((uint64_t)tiles + nt > 0x7FFFFFFFull) return fail(ctx, SPD_E_INVALID, "batch too large");
-            bd.push_back(BatchDesc{w.pairs, w.n, tiles, nsl - 1});
+            bd.push_back(BatchDesc{w.pairs, w.n, tiles, nsl - 1, w.swap, 0});
             tiles += (uint32_t)nt;
             as[nsl - 1].tile_hi = tiles;
         }
@@ -917,7 +924,7 @@ spd_status ctx_create(const spd_params *p, uint32_t n_routers, uint32_t n_slots,
 
 spd_status validate_batch(spd_ctx *ctx, const spd_batch &b) {
     if (b.router >= ctx->n_routers) return fail(ctx, SPD_E_STATE, "router id out of range");
-    if (b.reserved != 0) return fail(ctx, SPD_E_INVALID, "spd_batch.reserved must be 0");
+    if (b.flags & ~SPD_BATCH_DST) return fail(ctx, SPD_E_INVALID, "unknown spd_batch flags");
     if (b.n_pairs && !b.pairs_dev) return fail(ctx, SPD_E_INVALID, "null pair buffer");
     if (reinterpret_cast<uintptr_t>(b.pairs_dev) % 8) return fail(ctx, SPD_E_INVALID, "pair buffer must be 8-byte aligned");
     if (b.n_pairs > (1ull << 40)) return fail(ctx, SPD_E_INVALID, "batch too large");
@@ -975,7 +982,9 @@ spd_status spd_scan_batches(spd_ctx *ctx, const spd_batch *batches, uint32_t n_b
     for (uint32_t i = 0; i < n_batches; ++i) {
         spd_status st = validate_batch(ctx, batches[i]);
         if (st) return st;
-        if (batches[i].n_pairs) ws.push_back(WorkItem{&ctx->slots[batches[i].router], batches[i].pairs_dev, batches[i].n_pairs});
+        if (batches[i].n_pairs)
+            ws.push_back(WorkItem{&ctx->slots[batches[i].router], batches[i].pairs_dev, batches[i].n_pairs,
+                                  (batches[i].flags & SPD_BATCH_DST) ? 1u : 0u});
     }
     if (ws.empty()) return SPD_OK;
     DeviceGuard dg(ctx->device);
@@ -1387,7 +1396,7 @@ void srv_loop(spd_server *S) {
                 SrvPending &b = r.q.front();
                 uint64_t room = S->cfg.window_pairs ? S->cfg.window_pairs - r.in_window : UINT64_MAX;
                 uint64_t take = std::min(b.n, room);
-                if (take) group.push_back(WorkItem{&S->ctx->slots[r.slot], b.pairs, take});
+                if (take) group.push_back(WorkItem{&S->ctx->slots[r.slot], b.pairs, take, (b.flags & SPD_SUBMIT_DST) ? 1u : 0u});
                 gp += take;
                 r.in_window += take;
                 const bool whole = take == b.n;
@@ -1517,6 +1526,7 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
         st = ensure_scratch(ctx, items_words, meta_words, nullptr);
         if (!st && ctx->tune.bin_mode)
             st = ensure_aux(ctx, (uint64_t)kMaxGroup * g.nb + 1 + (tiles / kChunk + kMaxGroup) * g.nb, nullptr);
+        if (!st && ctx->tune.bin_mode) st = ensure_batch_ring(ctx, S->cfg.max_group_batches);
         if (st) {
             spd_server_destroy(S);
             return st;
@@ -1560,7 +1570,7 @@ spd_status spd_server_submit(spd_server *S, uint32_t router, const uint32_t *pai
     if (router >= S->cfg.n_routers) return SPD_E_STATE;
     if (n_pairs && !pairs_dev) return SPD_E_INVALID;
     if (reinterpret_cast<uintptr_t>(pairs_dev) % 8) return SPD_E_INVALID;
-    if (flags & ~SPD_SUBMIT_CLOSE) return SPD_E_INVALID;
+    if (flags & ~(SPD_SUBMIT_CLOSE | SPD_SUBMIT_DST)) return SPD_E_INVALID;
     const Clock::time_point t = Clock::now();
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->fault) return S->fault;

@@ -363,3 +363,76 @@ def test_many_batches_one_call_binned():
                 assert_same_sketch(det, r, oracle_sketch(mp, mine), f"router {r}")
         finally:
             det.close()
+
+
+def test_thousands_of_batches_one_call_bucket_major():
+    """More batches in one fused call than the descriptor ring holds at first (1024): the ring grows,
+    every tile finds its batch by binary search, and three routers' sketches equal the oracle's."""
+    mp = PARAMS["plain_1m"]
+    rng = np.random.default_rng(67)
+    pairs, _ = heavy_hosts(rng, 5, 2500, noise=1_400_000)
+    cuts = np.sort(rng.choice(np.arange(1, len(pairs)), size=1499, replace=False))
+    parts = np.split(pairs, cuts)
+    owner = rng.integers(0, 3, size=len(parts))
+    log(f"case {len(parts)} batches in one call, bucket-major")
+    det = detector(mp, n_routers=3, direct_max_pairs=0)
+    try:
+        x = to_dev(pairs)
+        starts = np.concatenate([[0], cuts])
+        det.scan_batches([(int(o), x[a:a + len(p)]) for o, a, p in zip(owner, starts, parts)])
+        for r in range(3):
+            mine = np.concatenate([p for o, p in zip(owner, parts) if o == r])
+            ref = oracle_sketch(mp, mine)
+            assert_same_sketch(det, r, ref, f"router {r}")
+            assert_same_report(det.close_window(r), ref.detect(), f"router {r}")
+    finally:
+        det.close()
+
+
+# ------------------------------------------------------------------------------ both directions
+@pytest.mark.parametrize("mode", ["direct", "binned_small", "binned_default", "bucket_major_small"])
+def test_both_directions_one_call(mode):
+    """Source-keyed and destination-keyed super points of the same pairs in one fused call: router 0
+    reads records as (hip, oip), router 1 as (oip, hip); each equals the oracle on the pairs as
+    given and on the swapped pairs."""
+    mp = PARAMS["plain_1m"]
+    rng = np.random.default_rng(83)
+    src_heavy, _ = heavy_hosts(rng, 4, 2500, noise=120_000)
+    dst_heavy, _ = heavy_hosts(rng, 4, 2500, noise=0)
+    pairs = np.concatenate([src_heavy, dst_heavy[:, ::-1]])   # super points on both sides
+    pairs = np.ascontiguousarray(pairs[rng.permutation(len(pairs))])
+    log(f"case both directions mode={mode}")
+    det = detector(mp, n_routers=2, **MODES[mode])
+    try:
+        x = to_dev(pairs)
+        half = len(pairs) // 2
+        det.scan_batches([(0, x[:half]), (1, x[:half], spd.BATCH_DST), (0, x[half:]), (1, x[half:], spd.BATCH_DST)])
+        for r, view in ((0, pairs), (1, np.ascontiguousarray(pairs[:, ::-1]))):
+            ref = oracle_sketch(mp, view)
+            assert_same_sketch(det, r, ref, f"router {r}")
+            got = det.close_window(r)
+            assert_same_report(got, ref.detect(), f"router {r}")
+            assert len(got) >= 4
+    finally:
+        det.close()
+
+
+def test_both_directions_sliding():
+    mp = st.CONFIGS["plain_1m"].params.replace(window_slices=3)
+    rng = np.random.default_rng(89)
+    p = oracle.params(mp)
+    det = detector(mp, n_routers=2)
+    sk = [oracle.SlidingSketch(p, 3), oracle.SlidingSketch(p, 3)]
+    try:
+        for t in range(4):
+            if t:
+                det.slide()
+            pairs, _ = heavy_hosts(rng, 2, 1500, noise=40_000)
+            x = to_dev(pairs)
+            det.scan_batches([(0, x), (1, x, spd.BATCH_DST)])
+            sk[0].scan_slice(pairs, t)
+            sk[1].scan_slice(np.ascontiguousarray(pairs[:, ::-1]), t)
+            for r in range(2):
+                assert_same_report(det.close_window(r), sk[r].bit_view(t).detect(), f"slice {t} router {r}")
+    finally:
+        det.close()

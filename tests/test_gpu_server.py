@@ -153,3 +153,25 @@ def test_serving_rejects_bad_requests():
         srv.close()
     with pytest.raises(spd.SpdError):
         spd.Server(spd.params_from(MP), n_routers=2, hbm_budget_bytes=1 << 20)
+
+
+def test_serving_destination_keyed_router():
+    """A router fed destination-keyed batches reports the super points of the opposite direction."""
+    rng = np.random.default_rng(31)
+    srv = spd.Server(spd.params_from(MP), n_routers=2, window_pairs=0, hbm_budget_bytes=512 << 20,
+                     max_group_pairs=2 << 20)
+    p = oracle.params(MP)
+    try:
+        pairs, _ = heavy_hosts(rng, 3, 2500, noise=150_000)
+        x = to_dev(pairs)
+        srv.submit(0, x, close=True)
+        srv.submit(1, x, close=True, dst=True)
+        got = {}
+        for _ in range(2):
+            hdr, sp = srv.next(timeout_ms=20000)
+            got[hdr["router"]] = sp
+        assert_same_report(got[0], oracle.Sketch(p).scan(pairs).detect(), "source-keyed")
+        assert_same_report(got[1], oracle.Sketch(p).scan(np.ascontiguousarray(pairs[:, ::-1])).detect(),
+                           "destination-keyed")
+    finally:
+        srv.close()
