@@ -129,6 +129,25 @@ def run_both_directions(spd, torch, params, x, steps, warmup):
     return x.shape[0] * steps / el, el / steps * 1e3, [int(len(r)) for r in rep]
 
 
+def run_host_ingest(spd, torch, params, pairs_np, steps, warmup):
+    """The window handed over in page-locked host memory: spd_scan_host copies it in 16 Mi-pair
+    chunks on its own stream, each copy overlapping the scan of the previous chunk, then the end of
+    window.  PCIe-inclusive pairs/s (the host link, not HBM, bounds this figure)."""
+    import numpy as np
+    host = torch.from_numpy(pairs_np.view(np.int32)).pin_memory()
+    det = spd.Detector(params)
+    for i in range(warmup + steps):
+        if i == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        det.scan_host(0, host)
+        det.close_window(0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    det.close()
+    return host.shape[0] * steps / el, el / steps * 1e3
+
+
 def bench_serving(spd, torch, np, st, capacity_pps, windows_per_router, load, log_fn):
     """The serving loop on the 16-router workload: batches of log-uniform size in [4Ki, 4Mi] pairs,
     Poisson arrivals at `load` x capacity_pps, a window closed every 64Mi pairs per router.  Router
@@ -317,6 +336,12 @@ def main() -> int:
     out["both_directions"] = {"value": bpps, "unit": "packets/s", "ms_per_step": bms,
                               "reported_super_points": {"source_keyed": bsizes[0], "destination_keyed": bsizes[1]},
                               "step": "scan of the window keyed both ways in one call + both ends of window"}
+
+    log("host ingestion: page-locked host buffer, double-buffered copies overlapping the scan")
+    hpps, hms = run_host_ingest(spd, torch, params, pairs, args.plain_steps, 1)
+    out["host_ingest"] = {"value": hpps, "unit": "packets/s", "ms_per_step": hms, "bytes_per_pair": BYTES_PER_PAIR,
+                          "host_link_GBps": hpps * BYTES_PER_PAIR / 1e9,
+                          "step": "64Mi pairs from pinned host memory (16Mi-pair chunks) + end of window"}
 
     if args.serving_windows > 0:
         log("serving loop: 16 routers")

@@ -162,6 +162,14 @@ void spd_destroy(spd_ctx *ctx);
  * Sliding mode: the pairs belong to the current slice.  n_pairs = 0 is a no-op. */
 spd_status spd_scan(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_dev, uint64_t n_pairs, void *stream);
 
+/* The same for pairs in HOST memory (the watch point's buffered copy to the GPU, Section 4.1):
+ * copied in chunks of chunk_pairs (0: 16 Mi) through two device staging buffers on a copy stream of
+ * the library, the copy of one chunk overlapping the scan of the previous one.  Page-locked host
+ * memory gives asynchronous copies; pageable memory works, with the copies synchronous.  flags:
+ * 0 or SPD_BATCH_DST.  Returns when every pair has been recorded (the host buffer may be reused). */
+spd_status spd_scan_host(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_host, uint64_t n_pairs, uint32_t flags,
+                         uint64_t chunk_pairs, void *stream);
+
 /* Record several batches, from any routers and of any sizes, in one fused pass (same result as
  * calling spd_scan on each batch). */
 spd_status spd_scan_batches(spd_ctx *ctx, const spd_batch *batches, uint32_t n_batches, void *stream);

@@ -87,7 +87,7 @@ class SpdServerStats(ctypes.Structure):
 
 RECORD = np.dtype([("ip", "<u4"), ("z0", "<u4"), ("est", "<u4"), ("flags", "<u4")])
 
-EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_batches", "spd_merge",
+EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_host", "spd_scan_batches", "spd_merge",
             "spd_close_window", "spd_slide", "spd_export", "spd_import", "spd_export_stamps",
             "spd_current_slice", "spd_get_tuning", "spd_set_tuning", "spd_get_stats", "spd_strerror",
             "spd_last_error", "spd_profile_enable", "spd_profile_select", "spd_get_profile", "spd_server_create", "spd_server_submit",
@@ -142,6 +142,7 @@ def lib(require_torch: bool = True) -> ctypes.CDLL:
         "spd_create": (i32, [P(SpdParams), u32, u64, P(vp)]),
         "spd_destroy": (None, [vp]),
         "spd_scan": (i32, [vp, u32, vp, u64, vp]),
+        "spd_scan_host": (i32, [vp, u32, vp, u64, u32, u64, vp]),
         "spd_scan_batches": (i32, [vp, P(SpdBatch), u32, vp]),
         "spd_merge": (i32, [vp, P(u32), u32, vp]),
         "spd_close_window": (i32, [vp, i32, P(SpdSuperpoint), u32, P(u32), vp]),
@@ -247,6 +248,23 @@ def spd_scan(ctx: int, router: int, pairs, stream=None) -> None:
 
 
 BATCH_DST = 1   # destination-keyed batch: records read as (oip, hip)
+
+
+def _host_pairs_ptr(pairs) -> Tuple[int, int, object]:
+    """(address, n, owner) of a host buffer of n (hip, oip) uint32 records: a numpy array or a CPU
+    torch tensor (page-locked when made with pin_memory=True)."""
+    if isinstance(pairs, np.ndarray):
+        if pairs.ndim != 2 or pairs.shape[1] != 2 or pairs.dtype.itemsize != 4 or not pairs.flags.c_contiguous:
+            raise ValueError("pairs must be a C-contiguous [n, 2] array of 4-byte elements")
+        return pairs.ctypes.data if pairs.size else 0, pairs.shape[0], pairs
+    if pairs.is_cuda or pairs.dim() != 2 or pairs.shape[1] != 2 or pairs.element_size() != 4 or not pairs.is_contiguous():
+        raise ValueError("pairs must be a contiguous CPU tensor of shape [n, 2] with 4-byte elements")
+    return (pairs.data_ptr() if pairs.numel() else 0), pairs.shape[0], pairs
+
+
+def spd_scan_host(ctx: int, router: int, pairs, flags: int = 0, chunk_pairs: int = 0, stream=None) -> None:
+    ptr, n, _owner = _host_pairs_ptr(pairs)
+    _check(lib().spd_scan_host(ctx, router, ptr or None, n, flags, chunk_pairs, _stream_ptr(stream)), ctx)
 
 
 def spd_scan_batches(ctx: int, batches: Iterable[Tuple], stream=None) -> None:
@@ -366,6 +384,10 @@ class Detector:
 
     def scan(self, router, pairs, stream=None):
         spd_scan(self.ctx, router, pairs, stream)
+
+    def scan_host(self, router, pairs, flags=0, chunk_pairs=0, stream=None):
+        """Pairs in host memory (numpy array or CPU tensor), copied in chunks overlapping the scan."""
+        spd_scan_host(self.ctx, router, pairs, flags, chunk_pairs, stream)
 
     def scan_batches(self, batches, stream=None):
         spd_scan_batches(self.ctx, batches, stream)

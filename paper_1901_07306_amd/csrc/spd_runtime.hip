@@ -83,6 +83,10 @@ struct spd_ctx {
     hipEvent_t bd_ev[kBdRing] = {};     // recorded after the last kernel that reads a slot
     uint32_t bd_cap = 0;                // descriptors per slot
     uint32_t bd_next = 0;
+    uint32_t *h2d_buf[2] = {};          // staging of spd_scan_host
+    uint64_t h2d_words = 0;             // per staging buffer
+    hipStream_t h2d_s = nullptr;
+    hipEvent_t h2d_copied[2] = {}, h2d_scanned[2] = {};
     uint32_t *aux = nullptr;         // bucket-major layout: padded bucket totals and their prefix
     uint64_t aux_words = 0;
     CloseBuf cbuf;                  // end-of-window buffers of spd_close_window
@@ -959,6 +963,12 @@ void spd_destroy(spd_ctx *ctx) {
         free_batch_ring(ctx);
         for (auto &e : ctx->bd_ev)
             if (e) (void)hipEventDestroy(e);
+        for (int k = 0; k < 2; ++k) {
+            dev_free(ctx, &ctx->h2d_buf[k], ctx->h2d_words * 4);
+            if (ctx->h2d_copied[k]) (void)hipEventDestroy(ctx->h2d_copied[k]);
+            if (ctx->h2d_scanned[k]) (void)hipEventDestroy(ctx->h2d_scanned[k]);
+        }
+        if (ctx->h2d_s) (void)hipStreamDestroy(ctx->h2d_s);
         close_buf_free(ctx, ctx->cbuf);
         dev_free(ctx, &ctx->view, ctx->view_words * 4);
         if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
@@ -972,6 +982,55 @@ spd_status spd_scan(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_dev, ui
     if (!ctx) return SPD_E_INVALID;
     spd_batch b{router, 0, pairs_dev, n_pairs};
     return spd_scan_batches(ctx, &b, 1, stream);
+}
+
+spd_status spd_scan_host(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_host, uint64_t n_pairs, uint32_t flags,
+                         uint64_t chunk_pairs, void *stream) {
+    if (!ctx) return SPD_E_INVALID;
+    if (router >= ctx->n_routers) return fail(ctx, SPD_E_STATE, "router id out of range");
+    if (flags & ~SPD_BATCH_DST) return fail(ctx, SPD_E_INVALID, "unknown flags");
+    if (n_pairs && !pairs_host) return fail(ctx, SPD_E_INVALID, "null pair buffer");
+    if (n_pairs > (1ull << 40)) return fail(ctx, SPD_E_INVALID, "batch too large");
+    if (n_pairs == 0) return SPD_OK;
+    if (chunk_pairs == 0) chunk_pairs = 16ull << 20;
+    chunk_pairs = std::min<uint64_t>(chunk_pairs, n_pairs);
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    order_stream(ctx, s);
+    if (!ctx->h2d_s) {
+        SPD_HIP(ctx, hipStreamCreateWithFlags(&ctx->h2d_s, hipStreamNonBlocking));
+        for (int k = 0; k < 2; ++k) {
+            SPD_HIP(ctx, hipEventCreateWithFlags(&ctx->h2d_copied[k], hipEventDisableTiming));
+            SPD_HIP(ctx, hipEventCreateWithFlags(&ctx->h2d_scanned[k], hipEventDisableTiming));
+        }
+    }
+    if (2 * chunk_pairs > ctx->h2d_words) {
+        SPD_HIP(ctx, hipStreamSynchronize(s));
+        for (int k = 0; k < 2; ++k) dev_free(ctx, &ctx->h2d_buf[k], ctx->h2d_words * 4);
+        ctx->h2d_words = 0;
+        for (int k = 0; k < 2; ++k) {
+            spd_status st = dev_alloc(ctx, &ctx->h2d_buf[k], chunk_pairs * 8);
+            if (st) return st;
+        }
+        ctx->h2d_words = 2 * chunk_pairs;
+    }
+    const uint32_t swap = (flags & SPD_BATCH_DST) ? 1u : 0u;
+    uint64_t i = 0;
+    for (uint64_t off = 0; off < n_pairs; off += chunk_pairs, ++i) {
+        const int k = (int)(i & 1);
+        const uint64_t cn = std::min(chunk_pairs, n_pairs - off);
+        // staging buffer k is free once the scan that last read it has run
+        SPD_HIP(ctx, hipStreamWaitEvent(ctx->h2d_s, ctx->h2d_scanned[k], 0));
+        SPD_HIP(ctx, hipMemcpyAsync(ctx->h2d_buf[k], pairs_host + 2 * off, cn * 8, hipMemcpyHostToDevice, ctx->h2d_s));
+        SPD_HIP(ctx, hipEventRecord(ctx->h2d_copied[k], ctx->h2d_s));
+        SPD_HIP(ctx, hipStreamWaitEvent(s, ctx->h2d_copied[k], 0));
+        std::vector<WorkItem> ws{WorkItem{&ctx->slots[router], ctx->h2d_buf[k], cn, swap}};
+        spd_status st = scan_work(ctx, ws, s);
+        if (st) return st;
+        SPD_HIP(ctx, hipEventRecord(ctx->h2d_scanned[k], s));
+    }
+    SPD_HIP(ctx, hipStreamSynchronize(s));
+    return SPD_OK;
 }
 
 spd_status spd_scan_batches(spd_ctx *ctx, const spd_batch *batches, uint32_t n_batches, void *stream) {

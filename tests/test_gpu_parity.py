@@ -436,3 +436,25 @@ def test_both_directions_sliding():
                 assert_same_report(det.close_window(r), sk[r].bit_view(t).detect(), f"slice {t} router {r}")
     finally:
         det.close()
+
+
+# ------------------------------------------------------------------------------ host ingestion
+@pytest.mark.parametrize("pinned", [False, True])
+def test_scan_from_host_memory(pinned):
+    """Pairs handed over in host memory, in chunks through the double-buffered staging (a ragged
+    last chunk; small chunks take the direct kernel, large ones the binned scan), both keyings."""
+    mp = PARAMS["plain_1m"]
+    rng = np.random.default_rng(97)
+    pairs, _ = heavy_hosts(rng, 5, 2500, noise=700_001)
+    host = torch.from_numpy(pairs.view(np.int32)).pin_memory() if pinned else pairs
+    log(f"case host ingestion pinned={pinned}")
+    det = detector(mp, n_routers=2)
+    try:
+        det.scan_host(0, host, chunk_pairs=300_000)
+        det.scan_host(1, host, flags=spd.BATCH_DST, chunk_pairs=100_000)
+        for r, view in ((0, pairs), (1, np.ascontiguousarray(pairs[:, ::-1]))):
+            ref = oracle_sketch(mp, view)
+            assert_same_sketch(det, r, ref, f"router {r}")
+            assert_same_report(det.close_window(r), ref.detect(), f"router {r}")
+    finally:
+        det.close()
