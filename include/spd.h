@@ -112,7 +112,12 @@ typedef struct spd_tuning {
                                   bucket-major layout: 4, 8 or 16 item words per lane */
     uint32_t bin_mode;         /* binned scan layout: 0 = per-tile regions (one pass over the pairs);
                                   1 = bucket-major (an exact counting pass first, then contiguous
-                                  per-bucket items that the apply phase streams) */
+                                  per-bucket items that the apply phase streams);
+                                  2 = per-(chunk of 128 tiles, bucket) regions of fixed capacity
+                                  (one pass over the pairs; words past a region's capacity are
+                                  recorded from a spill list after the apply phase) */
+    uint32_t region_words;     /* bin_mode 2: 64-bit words per region (0: derived from the expected
+                                  load of a bucket with a wide margin; small values force spills) */
 } spd_tuning;
 
 typedef struct spd_stats {
@@ -136,7 +141,8 @@ typedef struct spd_stats {
 #define SPD_K_FILL 7       /* clears (window reset, counters) */
 #define SPD_K_COUNT 8      /* bucket-major binned scan: exact per-tile counts */
 #define SPD_K_OFFSETS 9    /* bucket-major binned scan: per-tile segment offsets */
-#define SPD_K_KINDS 10
+#define SPD_K_SPILL 10     /* region layout: words past a region's capacity */
+#define SPD_K_KINDS 11
 
 typedef struct spd_profile {
     uint64_t launches[SPD_K_KINDS];

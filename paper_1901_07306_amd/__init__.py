@@ -50,7 +50,8 @@ class SpdBatch(ctypes.Structure):
 class SpdTuning(ctypes.Structure):
     _fields_ = [("direct_max_pairs", u64), ("bucket_bits", u32), ("tile_pairs", u32), ("bin_block", u32),
                 ("apply_block", u32), ("direct_block", u32), ("direct_grid_per_cu", u32), ("seav_lds", u32),
-                ("close_block", u32), ("launch_pairs", u64), ("apply_unroll", u32), ("bin_mode", u32)]
+                ("close_block", u32), ("launch_pairs", u64), ("apply_unroll", u32), ("bin_mode", u32),
+                ("region_words", u32)]
 
 
 class SpdStats(ctypes.Structure):
@@ -58,7 +59,7 @@ class SpdStats(ctypes.Structure):
                 ("candidates_last", u64), ("reported_last", u64), ("device_bytes", u64)]
 
 
-K_KINDS = ["direct", "stamp", "bin", "transpose", "apply", "merge", "close", "fill", "count", "offsets"]
+K_KINDS = ["direct", "stamp", "bin", "transpose", "apply", "merge", "close", "fill", "count", "offsets", "spill"]
 
 
 class SpdProfile(ctypes.Structure):

@@ -140,6 +140,41 @@ hipError_t launch_offsets(const uint32_t *cnt, uint32_t *loc, uint32_t *cstart, 
 hipError_t launch_place(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
                         uint32_t n_tiles, uint32_t *items, const uint32_t *cnt, const uint32_t *loc,
                         const uint32_t *cstart, const ChunkTable &ct, const SlotPtrs *slots, hipStream_t s);
+// Region layout of the binned scan (one pass over the pairs): every (chunk, bucket) has a region of
+// fixed capacity in `items`; a tile takes room for its padded segment of a bucket with one atomic
+// on that region's word count, and words past a region's capacity go to the spill list, which is
+// ORed into the sketches after the apply phase.  A slot's regions start at slot_base[s]: its full
+// chunks (kChunk tiles) first, chunk_words each (the LDCA buckets, capw_l words each, then the SEAV
+// buckets, capw_s words each), then its partial last chunk, if any, sized by its own tile count.
+struct RegionArgs {
+    uint64_t slot_base[kMaxGroup];
+    uint32_t full[kMaxGroup];                      // full chunks of each slot
+    uint32_t capl_last[kMaxGroup], caps_last[kMaxGroup];   // capacities of a partial last chunk
+    uint64_t *items;
+    uint32_t *cur;         // [chunks][nb] words taken in each region: zero before the launch, and
+                           // zeroed again by the apply phase once read
+    uint32_t *spill_n;     // overflow words of this launch (zero before the launch)
+    uint32_t *spill_next;  // the next launch's count: zeroed by this launch's spill phase
+    uint64_t *spill_w;     // [spill_cap] overflow words
+    uint32_t *spill_tag;   // [spill_cap] (slot << 16) | bucket of each overflow word
+    uint64_t chunk_words;  // nb_ldca * capw_l + (nb - nb_ldca) * capw_s
+    uint32_t capw_l, capw_s;
+    uint32_t spill_cap;    // at least the launch's padded words: the spill list cannot overflow
+    uint32_t pad;
+};
+hipError_t launch_clear(const ClearList &clear, hipStream_t s);
+// Region of chunk cc (counted inside slot si) for bucket b: its first word in items and its capacity.
+__host__ __device__ __forceinline__ uint64_t region_at(const RegionArgs &ra, uint32_t nb_ldca, uint32_t si,
+                                                       uint32_t cc, uint32_t b, uint32_t *capw) {
+    const bool last = cc >= ra.full[si];
+    const uint32_t cl = last ? ra.capl_last[si] : ra.capw_l, cs = last ? ra.caps_last[si] : ra.capw_s;
+    *capw = b < nb_ldca ? cl : cs;
+    const uint64_t in = b < nb_ldca ? (uint64_t)b * cl : (uint64_t)nb_ldca * cl + (uint64_t)(b - nb_ldca) * cs;
+    return ra.slot_base[si] + (uint64_t)cc * ra.chunk_words + in;
+}
+hipError_t launch_region(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
+                         uint32_t n_tiles, const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra,
+                         hipStream_t s);
 struct ApplySlot {
     uint32_t *ldca;
     uint32_t *seav_w;
@@ -151,6 +186,10 @@ hipError_t launch_apply(const BinGeometry &g, const ApplySlot *slots, uint32_t n
                         const uint32_t *metaT, uint32_t n_tiles, uint32_t block, uint32_t unroll, hipStream_t s);
 hipError_t launch_apply_bm(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
                            const uint32_t *base, uint32_t block, uint32_t unroll, hipStream_t s);
+hipError_t launch_apply_rg(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const ChunkTable &ct,
+                           const RegionArgs &ra, uint32_t block, uint32_t unroll, hipStream_t s);
+hipError_t launch_spill(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const RegionArgs &ra,
+                        hipStream_t s);
 hipError_t launch_or_merge(uint32_t *dst, const uint32_t *const *src, uint32_t n_src, uint64_t n_words, hipStream_t s);
 hipError_t launch_max_merge_u16(uint16_t *dst, const uint16_t *const *src, uint32_t n_src, uint64_t n_elems,
                                 hipStream_t s);

@@ -21,6 +21,13 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // A pair as the method sees it: (hip, oip) = the record, or the swapped record for a
 // destination-keyed batch (uniform per batch).
 __device__ __forceinline__ u32x2 keyed(u32x2 pr, uint32_t swap) { return swap ? u32x2{pr.y, pr.x} : pr; }
+// Pair i of a batch, keyed.  Batch pointers come from descriptors in memory, so the compiler
+// cannot tell their address space; naming it keeps these global (not flat) loads, which do not
+// hold up the LDS wait counter.
+typedef __attribute__((address_space(1))) const u32x2 global_u32x2;
+__device__ __forceinline__ u32x2 load_pair(const u32x2 *pairs, uint64_t i, uint32_t swap) {
+    return keyed(__builtin_nontemporal_load((const global_u32x2 *)pairs + i), swap);
+}
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct BatchTable {
@@ -130,7 +137,7 @@ __global__ __launch_bounds__(1024) void k_scan_direct(Consts c, BatchTable bt, S
         uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
         const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
         for (uint64_t i = gtid; i < B.n; i += stride) {
-            const u32x2 pr = keyed(__builtin_nontemporal_load(pairs + i), B.swap);
+            const u32x2 pr = load_pair(pairs, i, B.swap);
             const uint32_t hip = pr.x, oip = pr.y;
             const uint32_t q = ldc_bit(oip, c);
             for (uint32_t r = 0; r < c.lr; ++r) {
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(1024) void k_scan_stamp(Consts c, BatchTable bt, Sl
         const SlotPtrs S = st.s[B.slot];
         const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
         for (uint64_t i = gtid; i < B.n; i += stride) {
-            const u32x2 pr = keyed(__builtin_nontemporal_load(pairs + i), B.swap);
+            const u32x2 pr = load_pair(pairs, i, B.swap);
             const uint32_t hip = pr.x, oip = pr.y;
             const uint32_t q = ldc_bit(oip, c);
             for (uint32_t r = 0; r < c.lr; ++r) S.ldca_ts[ldca_bit(r, ldc_col(hip, r, c), q, c)] = v;
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
-        pr[j] = keyed(__builtin_nontemporal_load(pairs + (idx < B.n ? idx : last)), B.swap);
+        pr[j] = load_pair(pairs, idx < B.n ? idx : last, B.swap);
     }
     __syncthreads();
 
@@ -458,7 +465,7 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchL
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
-        pr[j] = keyed(__builtin_nontemporal_load(pairs + (idx < B.n ? idx : last)), B.swap);
+        pr[j] = load_pair(pairs, idx < B.n ? idx : last, B.swap);
     }
     // the SEAVs of fresh slots, spread over the whole grid (16-byte stores)
     {
@@ -575,14 +582,17 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchL
     const uint32_t *ctr = cnt + (uint64_t)tile * nb;
     const uint32_t *ot = off + (uint64_t)tile * nb;
     const uint32_t *cs0 = cstart + (uint64_t)chunk * nb;
-    uint32_t c_pre[2] = {0u, 0u}, o_pre[2] = {0u, 0u};
+    // (the two parts of an offset are added where they are used, so no wait comes before the pairs)
+    uint32_t c_pre[2] = {0u, 0u}, o_pre[2] = {0u, 0u}, s_pre[2] = {0u, 0u};
     if (tid < nb) {
         c_pre[0] = ctr[tid];
-        o_pre[0] = ot[tid] + cs0[tid];
+        o_pre[0] = ot[tid];
+        s_pre[0] = cs0[tid];
     }
     if (tid + BLOCK < nb) {
         c_pre[1] = ctr[tid + BLOCK];
-        o_pre[1] = ot[tid + BLOCK] + cs0[tid + BLOCK];
+        o_pre[1] = ot[tid + BLOCK];
+        s_pre[1] = cs0[tid + BLOCK];
     }
     const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
     const uint64_t last = B.n - 1;
@@ -590,7 +600,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchL
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
-        pr[j] = keyed(__builtin_nontemporal_load(pairs + (idx < B.n ? idx : last)), B.swap);
+        pr[j] = load_pair(pairs, idx < B.n ? idx : last, B.swap);
     }
     for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
         const uint32_t v = m == 0 ? c_pre[0] : m == 1 ? c_pre[1] : ctr[b];
@@ -640,7 +650,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchL
         const uint32_t e = cur[b], s0 = lb[b], pe = lb[b + 1];
         if (e > s0)
             for (uint32_t p = e; p < pe; ++p) stage[p] = stage[e - 1];
-        cur[b] = (m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : ot[b] + cs0[b]) / 3 - s0 / 3;
+        cur[b] = (m == 0 ? o_pre[0] + s_pre[0] : m == 1 ? o_pre[1] + s_pre[1] : ot[b] + cs0[b]) / 3 - s0 / 3;
     }
     __syncthreads();
     // one thread per stage word: the stage holds full bit addresses, so a word's first item names
@@ -735,6 +745,312 @@ hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *
                         uint32_t n_tiles, uint32_t *cnt, const ClearList &clear, hipStream_t s) {
     return launch_bin_kind(2, c, g, batches_dev, n_batches, n_tiles, nullptr, cnt, nullptr, nullptr, &clear, nullptr,
                            nullptr, s);
+}
+
+// ---- region layout (one pass over the pairs)
+
+// A tile's items binned in LDS as in k_bin (ranks per bucket, then segment bases), with each
+// bucket's segment padded to whole 64-bit words (copies of its last item).  Each non-empty segment
+// takes room in its (chunk, bucket) region with one atomic; the atomics are issued before the
+// items are placed in the stage, so their round trip overlaps that work.  The stage holds full
+// bit addresses, so a stage word's first item names its bucket at write-out, and the last two
+// places of each segment are first filled with an address of another bucket: those still holding
+// it after placement are the padding.  Where a lane's pairs and items need few enough registers,
+// they are held to 64 per lane, so that two workgroups of 1024 lanes share a compute unit.
+template <int LR, int PPT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4 * PPT + 3 * PPT * LR <= 80 ? 8 : 1))) void k_region(Consts c, BinGeometry g, BatchList bl, SlotTable st, ChunkTable ct,
+                                                  RegionArgs ra) {
+    extern __shared__ uint32_t lds[];
+    __shared__ RowLds rl;   // read after the first barrier
+    rows_to_lds(rl, c);
+    const uint32_t nb = g.nb;
+    uint32_t *cl = lds;                  // [nb + 1] LDCA counts, then padded counts, then bases
+    uint32_t *cs = cl + (nb + 1);        // [nb + 1] SEAV counts, then SEAV cursors
+    uint32_t *stage = lds + ((2 * (nb + 1) + 3) & ~3u);   // [cap] full bit addresses, bucket-major
+    uint32_t *samp = stage + g.cap;      // [2 * scap] sampled (hip, H2 bit)
+    uint32_t *misc = samp + 2 * g.scap;  // [0] sampled count, [1..17] scan scratch
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
+    const BatchDesc B = bl.b[find_batch(bl, tile)];
+    const SlotPtrs S = st.s[B.slot];
+    const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
+    const uint32_t cc = (tile - ct.lo[B.slot]) / kChunk, chunk = ct.cbase[B.slot] + cc;
+    const uint32_t seav_base = (uint32_t)c.ldca_bits;   // SEAV bits follow the LDCA bits
+
+    for (uint32_t i = tid; i < 2 * (nb + 1); i += BLOCK) cl[i] = 0;
+    if (tid == 0) misc[0] = 0;
+    const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+    const uint64_t last = B.n - 1;
+    u32x2 pr[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const uint64_t idx = p0 + (uint64_t)j * BLOCK + tid;
+        pr[j] = load_pair(pairs, idx < B.n ? idx : last, B.swap);
+    }
+    __syncthreads();
+    uint32_t bits[PPT * LR], rk[(PPT * LR + 1) / 2];
+    if (p0 + (uint64_t)(PPT * BLOCK) <= B.n)
+        bin_hash_pairs<LR, PPT, BLOCK, true>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
+    else
+        bin_hash_pairs<LR, PPT, BLOCK, false>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
+    __syncthreads();
+    // a tile with more sampled pairs than it can stage records all of them directly
+    uint32_t ns = misc[0];
+    if (ns > g.scap) {
+        uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
+        for (uint32_t e = tid; e < g.scap; e += BLOCK) {
+            const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
+            for (uint32_t r = 0; r < c.sr; ++r) {
+                const uint32_t bit = seav_byte_l(hip, r, rl, c) * 8u + b;
+                global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
+            }
+        }
+        ns = 0;
+    }
+    for (uint32_t w = tid; w < ns * c.sr; w += BLOCK) {
+        const uint32_t e = w / c.sr, r = w - e * c.sr;
+        const uint32_t bit = seav_base + seav_byte_l(samp[2 * e], r, rl, c) * 8u + samp[2 * e + 1];
+        atomicAdd(&cs[bit >> g.S], 1u);
+    }
+    __syncthreads();
+    // padded counts (whole words); bucket_offsets then leaves cl[b] = cs[b] = segment base
+    for (uint32_t b = tid; b < nb; b += BLOCK) {
+        const uint32_t n = cl[b] + cs[b];
+        cl[b] = 0;
+        cs[b] = (n + 2) / 3 * 3;
+    }
+    __syncthreads();
+    bucket_offsets<BLOCK>(cl, cs, nb, misc + 1);
+    // room in the regions (the offsets of a thread's first two buckets stay in flight), and the
+    // padding marks
+    uint32_t *rcur = ra.cur + (uint64_t)chunk * nb;
+    uint32_t o_pre[2] = {0u, 0u};
+    for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
+        const uint32_t s0 = cl[b], pe = cl[b + 1];
+        if (pe > s0) {
+            if (m < 2) o_pre[m] = atomicAdd(rcur + b, (pe - s0) / 3);
+            stage[pe - 2] = stage[pe - 1] = (b ^ 1u) << g.S;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT * LR; ++k) {
+        const uint32_t rank = (rk[k / 2] >> (16 * (k & 1))) & 0xFFFFu;
+        if (rank != 0xFFFFu) stage[cl[bits[k] >> g.S] + rank] = bits[k];
+    }
+    for (uint32_t w = tid; w < ns * c.sr; w += BLOCK) {
+        const uint32_t e = w / c.sr, r = w - e * c.sr;
+        const uint32_t bit = seav_base + seav_byte_l(samp[2 * e], r, rl, c) * 8u + samp[2 * e + 1];
+        stage[atomicAdd(&cs[bit >> g.S], 1u)] = bit;
+    }
+    __syncthreads();
+    // pad every segment with its last item; cs[b] becomes the distance in words from the stage to
+    // the region
+    for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
+        const uint32_t s0 = cl[b], pe = cl[b + 1];
+        uint32_t o = 0;
+        if (pe > s0) {
+            if ((stage[pe - 2] >> g.S) != b) stage[pe - 2] = stage[pe - 3];
+            if ((stage[pe - 1] >> g.S) != b) stage[pe - 1] = stage[pe - 2];
+            o = m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : atomicAdd(rcur + b, (pe - s0) / 3);
+        }
+        cs[b] = o - s0 / 3;
+    }
+    __syncthreads();
+    // one thread per stage word: three 21-bit offsets per 64-bit word
+    const uint32_t smask = (1u << g.S) - 1u;
+    const uint32_t nwords = cl[nb] / 3;
+    for (uint32_t w = tid; w < nwords; w += BLOCK) {
+        const uint32_t s0 = stage[3 * w], s1 = stage[3 * w + 1], s2 = stage[3 * w + 2];
+        const uint32_t b = s0 >> g.S;
+        const uint64_t v = (uint64_t)(s0 & smask) | ((uint64_t)(s1 & smask) << 21) | ((uint64_t)(s2 & smask) << 42);
+        const uint32_t rel = w + cs[b];
+        uint32_t capw;
+        const uint64_t at = region_at(ra, g.nb_ldca, B.slot, cc, b, &capw);
+        if (rel < capw) {
+            ra.items[at + rel] = v;
+        } else {
+            const uint32_t k = atomicAdd(ra.spill_n, 1u);
+            if (k < ra.spill_cap) {
+                ra.spill_w[k] = v;
+                ra.spill_tag[k] = (B.slot << 16) | b;
+            }
+        }
+    }
+}
+
+template <int LR>
+static hipError_t launch_region_lr(const Consts &c, const BinGeometry &g, const BatchList &bl, const SlotTable &st,
+                                   const ChunkTable &ct, const RegionArgs &ra, uint32_t n_tiles, hipStream_t s) {
+    const uint32_t ppt = g.tile_pairs / g.block;
+#define SPD_RG_CASE(B, P)                                                                                        \
+    else if (g.block == B && ppt == P)                                                                         \
+        hipLaunchKernelGGL((k_region<LR, P, B>), dim3(n_tiles), dim3(B), g.lds_bytes, s, c, g, bl, st, ct, ra);
+    if (false) {
+    }
+    SPD_RG_CASE(1024, 16) SPD_RG_CASE(1024, 8) SPD_RG_CASE(1024, 4) SPD_RG_CASE(512, 16) SPD_RG_CASE(512, 8)
+    SPD_RG_CASE(512, 4) SPD_RG_CASE(256, 16) SPD_RG_CASE(256, 8)
+#undef SPD_RG_CASE
+    else return hipErrorInvalidConfiguration;
+    return hipGetLastError();
+}
+
+hipError_t launch_region(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
+                         uint32_t n_tiles, const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra,
+                         hipStream_t s) {
+    if (n_batches == 0 || n_tiles == 0) return hipErrorInvalidValue;
+    BatchList bl{batches_dev, n_batches};
+    SlotTable st{};
+    for (uint32_t i = 0; i < ct.n; ++i) st.s[i] = slots[i];
+    switch (c.lr) {
+    case 1: return launch_region_lr<1>(c, g, bl, st, ct, ra, n_tiles, s);
+    case 2: return launch_region_lr<2>(c, g, bl, st, ct, ra, n_tiles, s);
+    case 3: return launch_region_lr<3>(c, g, bl, st, ct, ra, n_tiles, s);
+    case 4: return launch_region_lr<4>(c, g, bl, st, ct, ra, n_tiles, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Zeroes every buffer of a clear list (16-byte stores over the whole grid).
+__global__ __launch_bounds__(256) void k_clear(ClearList clr) {
+    const uint64_t gt = (uint64_t)blockIdx.x * 256 + threadIdx.x, stride = (uint64_t)gridDim.x * 256;
+    for (uint32_t k = 0; k < clr.n; ++k) {
+        u32x4 *p4 = reinterpret_cast<u32x4 *>(clr.p[k]);
+        for (uint64_t w = gt; w < clr.words[k] / 4; w += stride) p4[w] = u32x4{0u, 0u, 0u, 0u};
+    }
+}
+
+hipError_t launch_clear(const ClearList &clear, hipStream_t s) {
+    uint64_t words = 0;
+    for (uint32_t k = 0; k < clear.n; ++k) {
+        if (clear.words[k] % 4 || reinterpret_cast<uintptr_t>(clear.p[k]) % 16) return hipErrorInvalidValue;
+        words += clear.words[k];
+    }
+    if (words == 0) return hipSuccess;
+    const uint64_t want = (words / 4 + 255) / 256;
+    const uint32_t grid = (uint32_t)(want < 2048 ? (want ? want : 1) : 2048);
+    hipLaunchKernelGGL(k_clear, dim3(grid), dim3(256), 0, s, clear);
+    return hipGetLastError();
+}
+
+// Apply phase of the region layout: one workgroup per (slot, bucket) ORs the used part of the
+// bucket's region in each of the slot's chunks into an LDS bitmap.  Work is split into pieces of
+// 64 * U words (one per wavefront at a time); a piece past its region's fill is skipped.
+template <int BLOCK, int U>
+__global__ __launch_bounds__(BLOCK) void k_apply_rg(BinGeometry g, ApplyTable at, ChunkTable ct, RegionArgs ra) {
+    extern __shared__ uint32_t bm[];
+    constexpr uint32_t NW = BLOCK / 64, PIECE = 64 * U;
+    const uint32_t words = 1u << (g.S - 5);
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t blk = blockIdx.x;
+    const uint32_t si = blk / g.nb, b = blk % g.nb;
+    const ApplySlot A = at.s[si];
+    uint32_t *dst = b < g.nb_ldca ? A.ldca + (uint64_t)b * words : A.seav_w + (uint64_t)(b - g.nb_ldca) * words;
+    if (A.fresh && b < g.nb_ldca) {
+        for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = 0;
+    } else {
+        for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = dst[w];
+    }
+    __syncthreads();
+    const uint32_t c0 = ct.cbase[si], nch = ct.cbase[si + 1] - c0;
+    uint32_t capw;
+    (void)region_at(ra, g.nb_ldca, si, 0, b, &capw);   // the largest capacity of the slot's chunks
+    const uint32_t ppc = (capw + PIECE - 1) / PIECE;
+    for (uint32_t u = wid; u < nch * ppc; u += NW) {
+        const uint32_t cc = u / ppc, w0 = (u - cc * ppc) * PIECE;
+        uint32_t cap_c;
+        const uint64_t at = region_at(ra, g.nb_ldca, si, cc, b, &cap_c);
+        uint32_t len = ra.cur[(uint64_t)(c0 + cc) * g.nb + b];
+        len = len < cap_c ? len : cap_c;
+        if (w0 >= len) continue;
+        const uint64_t *src = ra.items + at;
+        uint64_t v[U];
+#pragma unroll
+        for (uint32_t k = 0; k < U; ++k) {
+            const uint32_t ww = w0 + k * 64 + lane;
+            v[k] = __builtin_nontemporal_load(src + (ww < len ? ww : len - 1));   // unconditional loads
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < U; ++k) {
+            if (w0 + k * 64 + lane >= len) continue;
+#pragma unroll
+            for (uint32_t f = 0; f < 3; ++f) {
+                const uint32_t it = (uint32_t)(v[k] >> (21 * f)) & 0x1FFFFFu;
+                atomicOr(&bm[it >> 5], 1u << (it & 31u));
+            }
+        }
+    }
+    __syncthreads();
+    // the region counters of this (slot, bucket) start the next launch at zero
+    for (uint32_t cc = tid; cc < nch; cc += BLOCK) ra.cur[(uint64_t)(c0 + cc) * g.nb + b] = 0u;
+    const uint32_t words4 = words / 4;
+    if (words4) {
+        for (uint32_t w = tid; w < words4; w += BLOCK)
+            reinterpret_cast<u32x4 *>(dst)[w] = reinterpret_cast<const u32x4 *>(bm)[w];
+    } else {
+        for (uint32_t w = tid; w < words; w += BLOCK) dst[w] = bm[w];
+    }
+}
+
+template <int U>
+static void launch_apply_rg_u(const BinGeometry &g, const ApplyTable &at, const ChunkTable &ct, const RegionArgs &ra,
+                              dim3 grid, uint32_t lds, uint32_t block, hipStream_t s) {
+    if (block == 1024) hipLaunchKernelGGL((k_apply_rg<1024, U>), grid, dim3(1024), lds, s, g, at, ct, ra);
+    else if (block == 512) hipLaunchKernelGGL((k_apply_rg<512, U>), grid, dim3(512), lds, s, g, at, ct, ra);
+    else hipLaunchKernelGGL((k_apply_rg<256, U>), grid, dim3(256), lds, s, g, at, ct, ra);
+}
+
+hipError_t launch_apply_rg(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const ChunkTable &ct,
+                           const RegionArgs &ra, uint32_t block, uint32_t unroll, hipStream_t s) {
+    ApplyTable at{};
+    if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup || ct.n != n_slots) return hipErrorInvalidValue;
+    if (block != 1024 && block != 512 && block != 256) return hipErrorInvalidConfiguration;
+    for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
+    const uint32_t lds = (1u << (g.S - 5)) * 4u;
+    dim3 grid(n_slots * g.nb);
+    switch (unroll) {
+    case 8: launch_apply_rg_u<4>(g, at, ct, ra, grid, lds, block, s); break;
+    case 16: launch_apply_rg_u<8>(g, at, ct, ra, grid, lds, block, s); break;
+    case 32: launch_apply_rg_u<16>(g, at, ct, ra, grid, lds, block, s); break;
+    default: return hipErrorInvalidConfiguration;
+    }
+    return hipGetLastError();
+}
+
+// The spill list (words that did not fit their region), ORed into the sketches with global atomics
+// after the apply phase has written every bucket back.  Normally empty.  The spill counts of
+// consecutive launches alternate between two words: this launch clears the next one's.
+__global__ __launch_bounds__(256) void k_spill(BinGeometry g, ApplyTable at, RegionArgs ra) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ra.spill_next = 0u;
+    __shared__ uint32_t *lp[kMaxGroup];
+    __shared__ uint32_t *sp[kMaxGroup];
+    if (threadIdx.x < (uint32_t)kMaxGroup) {
+        lp[threadIdx.x] = at.s[threadIdx.x].ldca;
+        sp[threadIdx.x] = at.s[threadIdx.x].seav_w;
+    }
+    __syncthreads();
+    const uint32_t n0 = *ra.spill_n, n = n0 < ra.spill_cap ? n0 : ra.spill_cap;
+    const uint32_t words = 1u << (g.S - 5);
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const uint64_t v = ra.spill_w[i];
+        const uint32_t tag = ra.spill_tag[i], si = tag >> 16, b = tag & 0xFFFFu;
+        uint32_t *dst = b < g.nb_ldca ? lp[si] + (uint64_t)b * words : sp[si] + (uint64_t)(b - g.nb_ldca) * words;
+#pragma unroll
+        for (uint32_t f = 0; f < 3; ++f) {
+            const uint32_t it = (uint32_t)(v >> (21 * f)) & 0x1FFFFFu;
+            global_or(dst + (it >> 5), 1u << (it & 31u));
+        }
+    }
+}
+
+hipError_t launch_spill(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const RegionArgs &ra,
+                        hipStream_t s) {
+    ApplyTable at{};
+    if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
+    hipLaunchKernelGGL(k_spill, dim3(256), dim3(256), 0, s, g, at, ra);
+    return hipGetLastError();
 }
 
 // ---- offsets of the bucket-major layout

@@ -89,6 +89,8 @@ struct spd_ctx {
     hipEvent_t h2d_copied[2] = {}, h2d_scanned[2] = {};
     uint32_t *aux = nullptr;         // bucket-major layout: padded bucket totals and their prefix
     uint64_t aux_words = 0;
+    bool aux_zero = false;           // region layout: every aux word is zero between launches
+    uint32_t spill_parity = 0;       // region layout: which of two spill counts the next launch uses
     CloseBuf cbuf;                  // end-of-window buffers of spd_close_window
     uint32_t *view = nullptr;       // sliding export: bit view words
     uint64_t view_words = 0;
@@ -224,7 +226,8 @@ void default_tuning(spd_tuning *t) {
     t->close_block = 256;
     t->launch_pairs = 0;
     t->apply_unroll = 16;
-    t->bin_mode = 1;
+    t->bin_mode = 2;
+    t->region_words = 0;
 }
 
 void order_stream(spd_ctx *ctx, hipStream_t s) {
@@ -434,6 +437,8 @@ spd_status ensure_aux(spd_ctx *ctx, uint64_t words, hipStream_t s) {
     SPD_HIP(ctx, hipStreamSynchronize(s));
     dev_free(ctx, &ctx->aux, ctx->aux_words * 4);
     ctx->aux_words = 0;
+    ctx->aux_zero = false;
+    words = (words + 3) / 4 * 4;
     spd_status st = dev_alloc(ctx, &ctx->aux, words * 4);
     if (st) return st;
     ctx->aux_words = words;
@@ -445,6 +450,88 @@ spd_status ensure_aux(spd_ctx *ctx, uint64_t words, hipStream_t s) {
 void scratch_need(const BinGeometry &g, uint32_t bin_mode, uint64_t tiles, uint64_t *items_words, uint64_t *meta_words) {
     *items_words = bin_mode == 0 ? tiles * g.region : (tiles * g.cap + 2) / 3 * 2 + 4;
     *meta_words = tiles * (g.nb + 1);
+}
+
+// Region layout: 64-bit words per (chunk, bucket) region of a chunk of t tiles whose bucket expects
+// E items: 1.25 E plus eight standard deviations of a binomial count, the padding of t tiles (at
+// most two items each) and a margin, three items per word.  Room past the fill costs memory, not
+// traffic.
+static uint32_t region_capw(double E, double t) {
+    return (uint32_t)std::ceil((1.25 * E + 8.0 * std::sqrt(E) + 2.0 * t + 64.0) / 3.0);
+}
+
+// Expected items per tile of one LDCA bucket and of one SEAV bucket.
+static void region_load(const spd_ctx *ctx, const BinGeometry &g, double *el, double *es) {
+    const double T = g.tile_pairs, bucket = std::ldexp(1.0, (int)g.S);
+    const double ldca_bits = (double)ctx->d.ldca_words * 32.0, seav_bits = (double)ctx->d.seav_bytes * 8.0;
+    *el = T * ctx->p.lr * std::min(bucket, ldca_bits) / ldca_bits;
+    *es = T / std::ldexp(1.0, (int)ctx->d.tau) * ctx->p.sr * std::min(bucket, seav_bits) / seav_bits;
+}
+
+static uint32_t region_cap(const spd_ctx *ctx, double e_tile, double t) {
+    return ctx->tune.region_words ? ctx->tune.region_words : region_capw(e_tile * t, t);
+}
+
+// The region layout of one launch over the slots of ct (pointers left null): items_words = 32-bit
+// words of the regions, the spill words and the spill tags; cur_words = two spill counts, two spare
+// words and the region counters, a multiple of 4.
+void region_layout(const spd_ctx *ctx, const BinGeometry &g, const ChunkTable &ct, uint64_t tiles, RegionArgs *ra,
+                   uint64_t *items_words, uint64_t *cur_words) {
+    double el, es;
+    region_load(ctx, g, &el, &es);
+    const uint64_t nbs = g.nb - g.nb_ldca;
+    *ra = RegionArgs{};
+    ra->capw_l = region_cap(ctx, el, kChunk);
+    ra->capw_s = region_cap(ctx, es, kChunk);
+    ra->chunk_words = (uint64_t)g.nb_ldca * ra->capw_l + nbs * ra->capw_s;
+    uint64_t words = 0;
+    for (uint32_t k = 0; k < ct.n; ++k) {
+        const uint32_t nt = ct.hi[k] - ct.lo[k], rem = nt % kChunk;
+        ra->slot_base[k] = words;
+        ra->full[k] = nt / kChunk;
+        ra->capl_last[k] = rem ? region_cap(ctx, el, rem) : ra->capw_l;
+        ra->caps_last[k] = rem ? region_cap(ctx, es, rem) : ra->capw_s;
+        words += ra->full[k] * ra->chunk_words + (rem ? g.nb_ldca * ra->capl_last[k] + nbs * ra->caps_last[k] : 0);
+    }
+    // every padded word of the launch fits the spill list: at most cap / 3 words per tile
+    ra->spill_cap = (uint32_t)std::min<uint64_t>(tiles * g.cap / 3, 0xFFFFFFFFull);
+    *items_words = words * 2 + (uint64_t)ra->spill_cap * 3;
+    *cur_words = (4 + (uint64_t)ct.cbase[ct.n] * g.nb + 3) / 4 * 4;
+}
+
+// Upper bound of region_layout's sizes over every launch of at most `tiles` tiles in at most
+// kMaxGroup slots.  A partial chunk of r tiles takes at most A r + B sqrt(r) + C words (A, B, C
+// from region_capw, the ceiling included in C), and over at most kMaxGroup partial chunks of R
+// tiles in all, sum sqrt(r) <= sqrt(kMaxGroup R).
+void region_bound(const spd_ctx *ctx, const BinGeometry &g, uint64_t tiles, uint64_t *items_words,
+                  uint64_t *cur_words) {
+    double el, es;
+    region_load(ctx, g, &el, &es);
+    const double nbl = g.nb_ldca, nbs = g.nb - g.nb_ldca;
+    double words;
+    if (ctx->tune.region_words) {
+        words = ((double)tiles + kMaxGroup) * (nbl + nbs) * ctx->tune.region_words;
+    } else {
+        const double chunk_words = nbl * region_capw(el * kChunk, kChunk) + nbs * region_capw(es * kChunk, kChunk);
+        const double R = (double)std::min<uint64_t>(tiles, (uint64_t)kMaxGroup * (kChunk - 1));
+        const double A = (nbl * (1.25 * el + 2.0) + nbs * (1.25 * es + 2.0)) / 3.0;
+        const double B = 8.0 * (nbl * std::sqrt(el) + nbs * std::sqrt(es)) / 3.0;
+        const double C = (nbl + nbs) * (64.0 / 3.0 + 1.0);
+        words = (double)(tiles / kChunk) * chunk_words + A * R + B * std::sqrt(kMaxGroup * R) + kMaxGroup * C;
+    }
+    const uint64_t spill = std::min<uint64_t>(tiles * g.cap / 3, 0xFFFFFFFFull);
+    *items_words = (uint64_t)std::ceil(words) * 2 + spill * 3;
+    *cur_words = (4 + (tiles / kChunk + kMaxGroup) * g.nb + 3) / 4 * 4;
+}
+
+void free_scratch(spd_ctx *ctx) {
+    dev_free(ctx, &ctx->items, ctx->items_words * 4);
+    dev_free(ctx, &ctx->meta, ctx->meta_words * 4);
+    dev_free(ctx, &ctx->metaT, ctx->meta_words * 4);
+    dev_free(ctx, &ctx->metaB, ctx->meta_words * 4);
+    dev_free(ctx, &ctx->aux, ctx->aux_words * 4);
+    ctx->items_words = ctx->meta_words = ctx->aux_words = 0;
+    ctx->aux_zero = false;
 }
 
 spd_status ensure_scratch(spd_ctx *ctx, uint64_t items_words, uint64_t meta_words, hipStream_t s) {
@@ -467,6 +554,66 @@ spd_status ensure_scratch(spd_ctx *ctx, uint64_t items_words, uint64_t meta_word
         if (st) return st;
         ctx->meta_words = meta_words;
     }
+    return SPD_OK;
+}
+
+// One group of the region layout: clear (fresh SEAVs, region counters), bin into the regions,
+// apply every (slot, bucket), then the spill list.  SPD_E_NOMEM (nothing enqueued) if its scratch
+// does not fit the HBM budget.
+spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<BatchDesc> &bd, uint32_t tiles,
+                         const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, uint32_t nsl, hipStream_t s) {
+    RegionArgs ra{};
+    uint64_t items_words = 0, cur_words = 0;
+    region_layout(ctx, g, ct, tiles, &ra, &items_words, &cur_words);
+    spd_status st = ensure_scratch(ctx, items_words, 0, s);
+    if (!st) st = ensure_aux(ctx, cur_words, s);
+    if (st) return st;
+    const uint64_t region_words = items_words - (uint64_t)ra.spill_cap * 3;   // 32-bit words
+    ra.items = reinterpret_cast<uint64_t *>(ctx->items);
+    ra.spill_w = reinterpret_cast<uint64_t *>(ctx->items + region_words);
+    ra.spill_tag = ctx->items + region_words + (uint64_t)ra.spill_cap * 2;
+    ra.spill_n = ctx->aux + ctx->spill_parity;
+    ra.spill_next = ctx->aux + (ctx->spill_parity ^ 1u);
+    ra.cur = ctx->aux + 4;
+    BatchDesc *bdev = nullptr;
+    st = upload_batches(ctx, bd, s, &bdev);
+    if (st) return st;
+    {
+        ProfScope ps(ctx, SPD_K_FILL, s);
+        ClearList cl{};
+        if (!ctx->aux_zero) {   // after (re)allocation, another layout's use, or a failed launch
+            cl.p[cl.n] = ctx->aux;
+            cl.words[cl.n++] = ctx->aux_words;
+        }
+        for (uint32_t k = 0; k < nsl; ++k) {
+            if (!as[k].fresh) continue;
+            if (cl.n == (uint32_t)kMaxGroup) {
+                SPD_HIP(ctx, launch_clear(cl, s));
+                cl.n = 0;
+            }
+            cl.p[cl.n] = as[k].seav_w;
+            cl.words[cl.n++] = ctx->seav_alloc / 4;
+        }
+        SPD_HIP(ctx, launch_clear(cl, s));
+    }
+    ctx->aux_zero = false;   // until the launch's apply and spill phases are enqueued
+    {
+        ProfScope ps(ctx, SPD_K_BIN, s);
+        SPD_HIP(ctx, launch_region(ctx->c, g, bdev, (uint32_t)bd.size(), tiles, ct, sp, ra, s));
+        // the staging slot may be rewritten once the binning kernel has read it
+        SPD_HIP(ctx, hipEventRecord(ctx->bd_ev[ctx->bd_next], s));
+        ctx->bd_next = (ctx->bd_next + 1) % kBdRing;
+    }
+    {
+        ProfScope ps(ctx, SPD_K_APPLY, s);
+        SPD_HIP(ctx, launch_apply_rg(g, as, nsl, ct, ra, ctx->tune.apply_block, ctx->tune.apply_unroll, s));
+    }
+    {
+        ProfScope ps(ctx, SPD_K_SPILL, s);
+        SPD_HIP(ctx, launch_spill(g, as, nsl, ra, s));
+    }
+    ctx->spill_parity ^= 1u;
+    ctx->aux_zero = true;
     return SPD_OK;
 }
 
@@ -608,10 +755,23 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                 ct.cbase[k + 1] = ct.cbase[k] + (as[k].tile_hi - as[k].tile_lo + kChunk - 1) / kChunk;
             }
             const uint32_t chunks = ct.cbase[nsl];
+            if (ctx->tune.bin_mode == 2) {
+                // the exact-count layout (less scratch) if the region layout does not fit the budget
+                spd_status st = region_launch(ctx, g, bd, tiles, ct, sp, as, nsl, s);
+                if (st && st != SPD_E_NOMEM) return st;
+                if (!st) {
+                    for (uint32_t k = 0; k < nsl; ++k)
+                        fresh_slots.erase(std::remove(fresh_slots.begin(), fresh_slots.end(), owner[k]),
+                                          fresh_slots.end());
+                    ctx->stats.binned_launches++;
+                    continue;
+                }
+            }
             spd_status st = ensure_scratch(ctx, items_words, meta_words, s);
             if (!st) st = ensure_aux(ctx, (uint64_t)nsl * g.nb + 1 + (uint64_t)chunks * g.nb, s);
             if (st) return st;
             uint32_t *base = ctx->aux, *cstart = ctx->aux + nsl * g.nb + 1;
+            ctx->aux_zero = false;
             // the batch descriptors go to device memory through a pinned staging ring
             BatchDesc *bdev = nullptr;
             st = upload_batches(ctx, bd, s, &bdev);
@@ -1246,7 +1406,7 @@ spd_status spd_set_tuning(spd_ctx *ctx, const spd_tuning *t) {
     if (t->direct_grid_per_cu < 1 || t->direct_grid_per_cu > 64) return fail(ctx, SPD_E_INVALID, "direct_grid_per_cu");
     if (t->close_block != 64 && t->close_block != 128 && t->close_block != 256) return fail(ctx, SPD_E_INVALID, "close_block");
     if (t->apply_unroll != 8 && t->apply_unroll != 16 && t->apply_unroll != 32) return fail(ctx, SPD_E_INVALID, "apply_unroll");
-    if (t->bin_mode > 1) return fail(ctx, SPD_E_INVALID, "bin_mode");
+    if (t->bin_mode > 2) return fail(ctx, SPD_E_INVALID, "bin_mode");
     ctx->tune = *t;
     BinGeometry g{};
     if (t->direct_max_pairs < UINT64_MAX && !bin_geometry(ctx, &g)) {
@@ -1580,11 +1740,30 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
     BinGeometry g{};
     if (bin_geometry(ctx, &g)) {
         const uint64_t tiles = S->cfg.max_group_pairs / g.tile_pairs + S->cfg.max_group_batches + 1;
-        uint64_t items_words, meta_words;
-        scratch_need(g, ctx->tune.bin_mode, tiles, &items_words, &meta_words);
-        st = ensure_scratch(ctx, items_words, meta_words, nullptr);
-        if (!st && ctx->tune.bin_mode)
-            st = ensure_aux(ctx, (uint64_t)kMaxGroup * g.nb + 1 + (tiles / kChunk + kMaxGroup) * g.nb, nullptr);
+        auto reserve = [&](uint32_t mode) {
+            uint64_t items_words, meta_words;
+            scratch_need(g, mode, tiles, &items_words, &meta_words);
+            uint64_t aux_words = (uint64_t)kMaxGroup * g.nb + 1 + (tiles / kChunk + kMaxGroup) * g.nb;
+            if (mode == 2) {
+                region_bound(ctx, g, tiles, &items_words, &aux_words);
+                meta_words = 0;
+            }
+            spd_status r = ensure_scratch(ctx, items_words, meta_words, nullptr);
+            if (!r && mode) r = ensure_aux(ctx, aux_words, nullptr);
+            return r;
+        };
+        st = reserve(ctx->tune.bin_mode);
+        if (ctx->tune.bin_mode == 2) {
+            // the region layout needs the most scratch: under a budget that would then hold no window
+            // slot, the server keeps the exact-count layout
+            const uint64_t one_slot = ctx->slot_bytes + (uint64_t)kRecInit * 8 + 64;
+            const bool room = ctx->held + one_slot <= ctx->budget;
+            if (st == SPD_E_NOMEM || (!st && !room)) {
+                free_scratch(ctx);
+                ctx->tune.bin_mode = 1;
+                st = reserve(1);
+            }
+        }
         if (!st && ctx->tune.bin_mode) st = ensure_batch_ring(ctx, S->cfg.max_group_batches);
         if (st) {
             spd_server_destroy(S);

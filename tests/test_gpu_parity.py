@@ -24,7 +24,7 @@ if not torch.cuda.is_available():
 import paper_1901_07306_amd as spd  # noqa: E402
 
 DIRECT = dict(direct_max_pairs=1 << 62)
-# bin_mode 0: per-tile item regions; the library default is the bucket-major layout (bin_mode 1)
+# bin_mode 0: per-tile item regions; the library default is the region layout (bin_mode 2)
 BINNED_SMALL = dict(direct_max_pairs=0, bin_mode=0, tile_pairs=2048, bucket_bits=12, bin_block=512, apply_block=256,
                     apply_unroll=8)
 BINNED_DEFAULT = dict(direct_max_pairs=0)
@@ -34,6 +34,13 @@ BUCKET_MAJOR = dict(direct_max_pairs=0, bin_mode=1)
 BUCKET_MAJOR_SMALL = dict(direct_max_pairs=0, bin_mode=1, tile_pairs=2048, bucket_bits=12, bin_block=512,
                           apply_block=256, launch_pairs=70_000)
 BUCKET_MAJOR_WIDE = dict(direct_max_pairs=0, bin_mode=1, tile_pairs=8192, apply_unroll=32)
+# bin_mode 2: fixed-capacity (chunk, bucket) regions; region_words forces words onto the spill list
+REGION = dict(direct_max_pairs=0, bin_mode=2)
+REGION_SMALL = dict(direct_max_pairs=0, bin_mode=2, tile_pairs=2048, bucket_bits=12, bin_block=512, apply_block=256,
+                    launch_pairs=70_000)
+REGION_SPILL = dict(direct_max_pairs=0, bin_mode=2, region_words=5, apply_unroll=8)
+REGION_SPILL_ALL = dict(direct_max_pairs=0, bin_mode=2, region_words=1, tile_pairs=4096, bin_block=512,
+                        apply_unroll=32)
 
 
 def detector(mp, n_routers=1, isb=None, ibn=None, **tune):
@@ -54,7 +61,8 @@ PARAMS = {
 
 MODES = {"direct": DIRECT, "binned_small": BINNED_SMALL, "binned_default": BINNED_DEFAULT,
          "binned_chunked": BINNED_CHUNKED, "bucket_major": BUCKET_MAJOR, "bucket_major_small": BUCKET_MAJOR_SMALL,
-         "bucket_major_wide": BUCKET_MAJOR_WIDE}
+         "bucket_major_wide": BUCKET_MAJOR_WIDE, "region": REGION, "region_small": REGION_SMALL,
+         "region_spill": REGION_SPILL, "region_spill_all": REGION_SPILL_ALL}
 
 
 @pytest.mark.parametrize("pname", list(PARAMS))
@@ -122,7 +130,7 @@ def test_oip_whose_h1_is_zero_is_sampled():
             det.close()
 
 
-@pytest.mark.parametrize("mode", ["direct", "binned_small", "bucket_major_small"])
+@pytest.mark.parametrize("mode", ["direct", "binned_small", "bucket_major_small", "region_small", "region_spill"])
 def test_routers_fused_batches_and_merge(mode):
     mp = PARAMS["tiny_r20_sr3"].replace(theta=512)
     log(f"case routers mode={mode}")
@@ -315,7 +323,7 @@ def test_plain_64m_full_window():
     want = ref.detect()
     x = to_dev(win.pairs[0])
     # default tuning (the configuration the benchmark times), then the per-tile item layout
-    for name, tune in (("default", {}), ("tiles", BINNED_TILES)):
+    for name, tune in (("default", {}), ("tiles", BINNED_TILES), ("bucket-major", BUCKET_MAJOR), ("regions", REGION)):
         log(f"case plain_64m full: gpu {name}")
         det = detector(w.params, **tune)
         try:
@@ -334,7 +342,7 @@ def test_bucket_major_overflow_tile_records_seav_directly():
     mp = st.CONFIGS["plain_64m"].params.replace(theta=8)    # tau = 0: every pair is sampled
     rng = np.random.default_rng(71)
     pairs, _ = heavy_hosts(rng, 40, 1200, noise=30_000)
-    for tune in (BUCKET_MAJOR, BUCKET_MAJOR_SMALL, BINNED_TILES):
+    for tune in (BUCKET_MAJOR, BUCKET_MAJOR_SMALL, BINNED_TILES, REGION, REGION_SMALL):
         det = detector(mp, **tune)
         try:
             det.scan(0, to_dev(pairs))
@@ -354,7 +362,7 @@ def test_many_batches_one_call_binned():
     cuts = np.sort(rng.choice(np.arange(1, len(pairs)), size=70, replace=False))
     parts = np.split(pairs, cuts)
     owner = [0 if i % 3 else 1 for i in range(len(parts))]
-    for tune in (BINNED_SMALL, BUCKET_MAJOR_SMALL):
+    for tune in (BINNED_SMALL, BUCKET_MAJOR_SMALL, REGION_SMALL, REGION_SPILL):
         det = detector(mp, n_routers=2, **tune)
         try:
             det.scan_batches([(o, to_dev(p)) for o, p in zip(owner, parts)])
@@ -365,7 +373,8 @@ def test_many_batches_one_call_binned():
             det.close()
 
 
-def test_thousands_of_batches_one_call_bucket_major():
+@pytest.mark.parametrize("layout", [1, 2])
+def test_thousands_of_batches_one_call(layout):
     """More batches in one fused call than the descriptor ring holds at first (1024): the ring grows,
     every tile finds its batch by binary search, and three routers' sketches equal the oracle's."""
     mp = PARAMS["plain_1m"]
@@ -374,8 +383,8 @@ def test_thousands_of_batches_one_call_bucket_major():
     cuts = np.sort(rng.choice(np.arange(1, len(pairs)), size=1499, replace=False))
     parts = np.split(pairs, cuts)
     owner = rng.integers(0, 3, size=len(parts))
-    log(f"case {len(parts)} batches in one call, bucket-major")
-    det = detector(mp, n_routers=3, direct_max_pairs=0)
+    log(f"case {len(parts)} batches in one call, bin_mode {layout}")
+    det = detector(mp, n_routers=3, direct_max_pairs=0, bin_mode=layout)
     try:
         x = to_dev(pairs)
         starts = np.concatenate([[0], cuts])
@@ -390,7 +399,7 @@ def test_thousands_of_batches_one_call_bucket_major():
 
 
 # ------------------------------------------------------------------------------ both directions
-@pytest.mark.parametrize("mode", ["direct", "binned_small", "binned_default", "bucket_major_small"])
+@pytest.mark.parametrize("mode", ["direct", "binned_small", "binned_default", "bucket_major_small", "region_spill"])
 def test_both_directions_one_call(mode):
     """Source-keyed and destination-keyed super points of the same pairs in one fused call: router 0
     reads records as (hip, oip), router 1 as (oip, hip); each equals the oracle on the pairs as
