@@ -163,14 +163,18 @@ struct RegionArgs {
     uint32_t pad;
 };
 hipError_t launch_clear(const ClearList &clear, hipStream_t s);
-// Region of chunk cc (counted inside slot si) for bucket b: its first word in items and its capacity.
-__host__ __device__ __forceinline__ uint64_t region_at(const RegionArgs &ra, uint32_t nb_ldca, uint32_t si,
+// Region of chunk cc (counted inside slot si) for bucket b: its first word counted from the chunk's
+// first word (below 2^31: the host checks chunk sizes), and its capacity.
+__host__ __device__ __forceinline__ uint32_t region_in(const RegionArgs &ra, uint32_t nb_ldca, uint32_t si,
                                                        uint32_t cc, uint32_t b, uint32_t *capw) {
     const bool last = cc >= ra.full[si];
     const uint32_t cl = last ? ra.capl_last[si] : ra.capw_l, cs = last ? ra.caps_last[si] : ra.capw_s;
     *capw = b < nb_ldca ? cl : cs;
-    const uint64_t in = b < nb_ldca ? (uint64_t)b * cl : (uint64_t)nb_ldca * cl + (uint64_t)(b - nb_ldca) * cs;
-    return ra.slot_base[si] + (uint64_t)cc * ra.chunk_words + in;
+    return b < nb_ldca ? b * cl : nb_ldca * cl + (b - nb_ldca) * cs;
+}
+// First word of chunk cc of slot si in items.
+__host__ __device__ __forceinline__ uint64_t chunk_at(const RegionArgs &ra, uint32_t si, uint32_t cc) {
+    return ra.slot_base[si] + (uint64_t)cc * ra.chunk_words;
 }
 hipError_t launch_region(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
                          uint32_t n_tiles, const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra,
@@ -212,5 +216,7 @@ struct CloseArgs {
 };
 hipError_t launch_close(const Consts &c, const CloseArgs &a, bool sliding, uint32_t block, uint32_t grid,
                         hipStream_t s);
+// Workgroups of the end-of-window kernel that one compute unit holds at once (registers and LDS).
+uint32_t close_blocks_per_cu(bool sliding, uint32_t block, uint32_t lds_bytes);
 
 }  // namespace spd

@@ -833,10 +833,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4 * PPT +
         }
     }
     __syncthreads();
+    if (p0 + (uint64_t)(PPT * BLOCK) <= B.n) {   // every lane's items are valid
 #pragma unroll
-    for (int k = 0; k < PPT * LR; ++k) {
-        const uint32_t rank = (rk[k / 2] >> (16 * (k & 1))) & 0xFFFFu;
-        if (rank != 0xFFFFu) stage[cl[bits[k] >> g.S] + rank] = bits[k];
+        for (int k = 0; k < PPT * LR; ++k)
+            stage[cl[bits[k] >> g.S] + ((rk[k / 2] >> (16 * (k & 1))) & 0xFFFFu)] = bits[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < PPT * LR; ++k) {
+            const uint32_t rank = (rk[k / 2] >> (16 * (k & 1))) & 0xFFFFu;
+            if (rank != 0xFFFFu) stage[cl[bits[k] >> g.S] + rank] = bits[k];
+        }
     }
     for (uint32_t w = tid; w < ns * c.sr; w += BLOCK) {
         const uint32_t e = w / c.sr, r = w - e * c.sr;
@@ -844,31 +850,38 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4 * PPT +
         stage[atomicAdd(&cs[bit >> g.S], 1u)] = bit;
     }
     __syncthreads();
-    // pad every segment with its last item; cs[b] becomes the distance in words from the stage to
-    // the region
+    // pad every segment with its last item (the room of a thread's buckets past its first two is
+    // taken here, its offset kept in cs)
     for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
         const uint32_t s0 = cl[b], pe = cl[b + 1];
-        uint32_t o = 0;
         if (pe > s0) {
             if ((stage[pe - 2] >> g.S) != b) stage[pe - 2] = stage[pe - 3];
             if ((stage[pe - 1] >> g.S) != b) stage[pe - 1] = stage[pe - 2];
-            o = m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : atomicAdd(rcur + b, (pe - s0) / 3);
+            if (m >= 2) cs[b] = atomicAdd(rcur + b, (pe - s0) / 3);
         }
-        cs[b] = o - s0 / 3;
+    }
+    __syncthreads();
+    // per bucket, in stage words: cl[b] = the first word past the region's room, cs[b] = the
+    // distance from a word's place in the stage to its place among the chunk's regions
+    for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
+        const uint32_t w0 = cl[b] / 3, o = m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : cs[b];
+        uint32_t capw;
+        const uint32_t in = region_in(ra, g.nb_ldca, B.slot, cc, b, &capw);
+        cl[b] = w0 + (o < capw ? capw - o : 0u);
+        cs[b] = in + o - w0;
     }
     __syncthreads();
     // one thread per stage word: three 21-bit offsets per 64-bit word
     const uint32_t smask = (1u << g.S) - 1u;
     const uint32_t nwords = cl[nb] / 3;
+    uint64_t *dst = ra.items + chunk_at(ra, B.slot, cc);
     for (uint32_t w = tid; w < nwords; w += BLOCK) {
         const uint32_t s0 = stage[3 * w], s1 = stage[3 * w + 1], s2 = stage[3 * w + 2];
         const uint32_t b = s0 >> g.S;
-        const uint64_t v = (uint64_t)(s0 & smask) | ((uint64_t)(s1 & smask) << 21) | ((uint64_t)(s2 & smask) << 42);
-        const uint32_t rel = w + cs[b];
-        uint32_t capw;
-        const uint64_t at = region_at(ra, g.nb_ldca, B.slot, cc, b, &capw);
-        if (rel < capw) {
-            ra.items[at + rel] = v;
+        const uint32_t lo = (s0 & smask) | (s1 << 21), hi = ((s1 & smask) >> 11) | ((s2 & smask) << 10);
+        const uint64_t v = (uint64_t)lo | ((uint64_t)hi << 32);
+        if (w < cl[b]) {
+            dst[w + cs[b]] = v;
         } else {
             const uint32_t k = atomicAdd(ra.spill_n, 1u);
             if (k < ra.spill_cap) {
@@ -927,8 +940,9 @@ hipError_t launch_clear(const ClearList &clear, hipStream_t s) {
         words += clear.words[k];
     }
     if (words == 0) return hipSuccess;
-    const uint64_t want = (words / 4 + 255) / 256;
-    const uint32_t grid = (uint32_t)(want < 2048 ? (want ? want : 1) : 2048);
+    // about eight 16-byte stores per lane: few waves to launch
+    const uint64_t want = (words / 4 + 2047) / 2048;
+    const uint32_t grid = (uint32_t)(want < 1024 ? (want ? want : 1) : 1024);
     hipLaunchKernelGGL(k_clear, dim3(grid), dim3(256), 0, s, clear);
     return hipGetLastError();
 }
@@ -955,12 +969,12 @@ __global__ __launch_bounds__(BLOCK) void k_apply_rg(BinGeometry g, ApplyTable at
     __syncthreads();
     const uint32_t c0 = ct.cbase[si], nch = ct.cbase[si + 1] - c0;
     uint32_t capw;
-    (void)region_at(ra, g.nb_ldca, si, 0, b, &capw);   // the largest capacity of the slot's chunks
+    (void)region_in(ra, g.nb_ldca, si, 0, b, &capw);   // the largest capacity of the slot's chunks
     const uint32_t ppc = (capw + PIECE - 1) / PIECE;
     for (uint32_t u = wid; u < nch * ppc; u += NW) {
         const uint32_t cc = u / ppc, w0 = (u - cc * ppc) * PIECE;
         uint32_t cap_c;
-        const uint64_t at = region_at(ra, g.nb_ldca, si, cc, b, &cap_c);
+        const uint64_t at = chunk_at(ra, si, cc) + region_in(ra, g.nb_ldca, si, cc, b, &cap_c);
         uint32_t len = ra.cur[(uint64_t)(c0 + cc) * g.nb + b];
         len = len < cap_c ? len : cap_c;
         if (w0 >= len) continue;
@@ -1049,7 +1063,7 @@ hipError_t launch_spill(const BinGeometry &g, const ApplySlot *slots, uint32_t n
     ApplyTable at{};
     if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
     for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
-    hipLaunchKernelGGL(k_spill, dim3(256), dim3(256), 0, s, g, at, ra);
+    hipLaunchKernelGGL(k_spill, dim3(32), dim3(256), 0, s, g, at, ra);   // normally nothing to do
     return hipGetLastError();
 }
 
@@ -1535,7 +1549,7 @@ __device__ void filter_queue(const CloseArgs &a, const Consts &c, const uint32_t
 }
 
 template <bool SLIDING, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_close(Consts c, CloseArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_close(Consts c, CloseArgs a) {
     extern __shared__ uint32_t lds[];
     constexpr uint32_t NW = BLOCK / 64;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
@@ -1589,19 +1603,26 @@ __global__ __launch_bounds__(BLOCK) void k_close(Consts c, CloseArgs a) {
         for (uint32_t i = 0; i < c.sr; ++i) total *= cnt[i];
         uint32_t qn = 0;
         if (total <= lmask + 1ull) {
-            // the product CIS of the hot lists (Section 3.2), one tuple per lane
+            // the product CIS of the hot lists (Section 3.2), one tuple per lane.  A lane's tuple
+            // index is kept as mixed-radix digits (row 0 least significant) and advanced by 64 each
+            // round with a precomputed digit step, without division.
+            uint32_t dg[kMaxRows];
+            {
+                uint32_t rem = lane;
+                for (uint32_t i = 0; i < c.sr; ++i) {
+                    dg[i] = rem % cnt[i];
+                    rem /= cnt[i];
+                }
+            }
             for (uint64_t u0 = 0; u0 < total; u0 += 64) {
                 const uint64_t u = u0 + lane;
                 bool cand = false;
                 uint32_t h = 0;
                 if (u < total) {
-                    uint64_t rem = u;
                     uint32_t lp = 0, seu = 0xFFu;
                     uint32_t ci[kMaxRows];
                     for (uint32_t i = 0; i < c.sr; ++i) {
-                        uint32_t d = (uint32_t)(rem % cnt[i]);
-                        rem /= cnt[i];
-                        uint32_t e = lists[i * a.list_stride + d];
+                        uint32_t e = lists[i * a.list_stride + dg[i]];
                         ci[i] = e >> 8;
                         seu &= e & 0xFFu;
                         lp |= row_bits_in_lp(ci[i], c.isb[i], c.L);
@@ -1613,6 +1634,15 @@ __global__ __launch_bounds__(BLOCK) void k_close(Consts c, CloseArgs a) {
                         cand = true;
                         h = (uint32_t)(((uint64_t)lp << c.r) | rp);
                     }
+                }
+                // advance the digits by 64, whose digits are (64 mod cnt[0], (64 / cnt[0]) mod cnt[1], ...);
+                // each sum stays below twice its radix, so it wraps at most once
+                uint32_t carry = 0, inc = 64;
+                for (uint32_t i = 0; i < c.sr; ++i) {
+                    const uint32_t d = dg[i] + inc % cnt[i] + carry;
+                    inc /= cnt[i];
+                    carry = d >= cnt[i] ? 1u : 0u;
+                    dg[i] = carry ? d - cnt[i] : d;
                 }
                 const uint64_t bal = __ballot(cand);
                 if (cand) queue[qn + __popcll(bal & lane_lt)] = h;
@@ -1660,6 +1690,18 @@ __global__ __launch_bounds__(BLOCK) void k_close(Consts c, CloseArgs a) {
         for (uint32_t w = 0; w < NW; ++w) sum += wave_cand[w];
         if (sum) atomicAdd(&a.counters[1], sum);
     }
+}
+
+uint32_t close_blocks_per_cu(bool sliding, uint32_t block, uint32_t lds_bytes) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (block == 256) e = sliding ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<true, 256>, 256, lds_bytes)
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<false, 256>, 256, lds_bytes);
+    else if (block == 128) e = sliding ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<true, 128>, 128, lds_bytes)
+                                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<false, 128>, 128, lds_bytes);
+    else if (block == 64) e = sliding ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<true, 64>, 64, lds_bytes)
+                                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<false, 64>, 64, lds_bytes);
+    return (e == hipSuccess && n > 0) ? (uint32_t)n : 1u;
 }
 
 hipError_t launch_close(const Consts &c, const CloseArgs &a, bool sliding, uint32_t block, uint32_t grid, hipStream_t s) {

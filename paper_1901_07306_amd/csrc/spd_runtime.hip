@@ -90,6 +90,7 @@ struct spd_ctx {
     uint32_t *aux = nullptr;         // bucket-major layout: padded bucket totals and their prefix
     uint64_t aux_words = 0;
     bool aux_zero = false;           // region layout: every aux word is zero between launches
+    uint32_t close_per_cu[3] = {0, 0, 0};   // resident end-of-window workgroups per CU (64, 128, 256 lanes)
     uint32_t spill_parity = 0;       // region layout: which of two spill counts the next launch uses
     CloseBuf cbuf;                  // end-of-window buffers of spd_close_window
     uint32_t *view = nullptr;       // sliding export: bit view words
@@ -565,6 +566,7 @@ spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<B
     RegionArgs ra{};
     uint64_t items_words = 0, cur_words = 0;
     region_layout(ctx, g, ct, tiles, &ra, &items_words, &cur_words);
+    if (ra.chunk_words >= (1ull << 31)) return fail(ctx, SPD_E_INVALID, "region layout: chunk too large");
     spd_status st = ensure_scratch(ctx, items_words, 0, s);
     if (!st) st = ensure_aux(ctx, cur_words, s);
     if (st) return st;
@@ -877,7 +879,10 @@ spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArg
     const uint32_t waves = b / 64;
     const uint64_t want = ((uint64_t)a->n_rp + waves - 1) / waves;
     *block = b;
-    *grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)ctx->n_cu * 8));
+    // one round of resident workgroups; each wavefront then takes SEAs round robin
+    if (!ctx->close_per_cu[b / 128]) ctx->close_per_cu[b / 128] = close_blocks_per_cu(ctx->sliding, b, (uint32_t)((b / 64) * per_wave * 4));
+    const uint64_t resident = (uint64_t)ctx->n_cu * ctx->close_per_cu[b / 128];
+    *grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, resident));
     return SPD_OK;
 }
 
@@ -1407,6 +1412,7 @@ spd_status spd_set_tuning(spd_ctx *ctx, const spd_tuning *t) {
     if (t->close_block != 64 && t->close_block != 128 && t->close_block != 256) return fail(ctx, SPD_E_INVALID, "close_block");
     if (t->apply_unroll != 8 && t->apply_unroll != 16 && t->apply_unroll != 32) return fail(ctx, SPD_E_INVALID, "apply_unroll");
     if (t->bin_mode > 2) return fail(ctx, SPD_E_INVALID, "bin_mode");
+    if (t->region_words > (1u << 24)) return fail(ctx, SPD_E_INVALID, "region_words");
     ctx->tune = *t;
     BinGeometry g{};
     if (t->direct_max_pairs < UINT64_MAX && !bin_geometry(ctx, &g)) {
