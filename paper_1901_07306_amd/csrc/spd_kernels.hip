@@ -755,10 +755,9 @@ hipError_t launch_count(const Consts &c, const BinGeometry &g, const BatchDesc *
 // items are placed in the stage, so their round trip overlaps that work.  The stage holds full
 // bit addresses, so a stage word's first item names its bucket at write-out, and the last two
 // places of each segment are first filled with an address of another bucket: those still holding
-// it after placement are the padding.  Where a lane's pairs and items need few enough registers,
-// they are held to 64 per lane, so that two workgroups of 1024 lanes share a compute unit.
+// it after placement are the padding.
 template <int LR, int PPT, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4 * PPT + 3 * PPT * LR <= 80 ? 8 : 1))) void k_region(Consts c, BinGeometry g, BatchList bl, SlotTable st, ChunkTable ct,
+__global__ __launch_bounds__(BLOCK) void k_region(Consts c, BinGeometry g, BatchList bl, SlotTable st, ChunkTable ct,
                                                   RegionArgs ra) {
     extern __shared__ uint32_t lds[];
     __shared__ RowLds rl;   // read after the first barrier
@@ -823,12 +822,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4 * PPT +
     bucket_offsets<BLOCK>(cl, cs, nb, misc + 1);
     // room in the regions (the offsets of a thread's first two buckets stay in flight), and the
     // padding marks
+    // (two named registers: an array indexed by the loop counter would live in scratch memory)
     uint32_t *rcur = ra.cur + (uint64_t)chunk * nb;
-    uint32_t o_pre[2] = {0u, 0u};
+    uint32_t o_pre0 = 0u, o_pre1 = 0u;
     for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
         const uint32_t s0 = cl[b], pe = cl[b + 1];
         if (pe > s0) {
-            if (m < 2) o_pre[m] = atomicAdd(rcur + b, (pe - s0) / 3);
+            if (m == 0) o_pre0 = atomicAdd(rcur + b, (pe - s0) / 3);
+            else if (m == 1) o_pre1 = atomicAdd(rcur + b, (pe - s0) / 3);
             stage[pe - 2] = stage[pe - 1] = (b ^ 1u) << g.S;
         }
     }
@@ -864,7 +865,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4 * PPT +
     // per bucket, in stage words: cl[b] = the first word past the region's room, cs[b] = the
     // distance from a word's place in the stage to its place among the chunk's regions
     for (uint32_t b = tid, m = 0; b < nb; b += BLOCK, ++m) {
-        const uint32_t w0 = cl[b] / 3, o = m == 0 ? o_pre[0] : m == 1 ? o_pre[1] : cs[b];
+        const uint32_t w0 = cl[b] / 3, o = m == 0 ? o_pre0 : m == 1 ? o_pre1 : cs[b];
         uint32_t capw;
         const uint32_t in = region_in(ra, g.nb_ldca, B.slot, cc, b, &capw);
         cl[b] = w0 + (o < capw ? capw - o : 0u);
