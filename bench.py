@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, public figure
 BYTES_PER_PAIR = 8             # algorithmic HBM bytes per pair: one uint32 (hip, oip) record
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "place_kernel_plain_64m_traffic.txt")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "region_kernel_plain_64m_traffic.txt")
 
 
 def log(*a):
