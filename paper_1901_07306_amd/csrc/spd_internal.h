@@ -94,6 +94,15 @@ struct BatchDesc {
     uint32_t pad;
 };
 
+// Batches of a launch: in device memory (b, any number), or, with b null, up to kInlineBatches
+// copies carried in the kernel arguments; sorted by first_tile.
+constexpr uint32_t kInlineBatches = 8;
+struct BatchList {
+    const BatchDesc *b;
+    uint32_t n;
+    BatchDesc inl[kInlineBatches];
+};
+
 struct BinGeometry {
     uint32_t S;          // log2 of bits per bucket
     uint32_t nb_ldca;    // buckets covering the LDCA
@@ -176,9 +185,8 @@ __host__ __device__ __forceinline__ uint32_t region_in(const RegionArgs &ra, uin
 __host__ __device__ __forceinline__ uint64_t chunk_at(const RegionArgs &ra, uint32_t si, uint32_t cc) {
     return ra.slot_base[si] + (uint64_t)cc * ra.chunk_words;
 }
-hipError_t launch_region(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
-                         uint32_t n_tiles, const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra,
-                         hipStream_t s);
+hipError_t launch_region(const Consts &c, const BinGeometry &g, const BatchList &bl, uint32_t n_tiles,
+                         const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra, hipStream_t s);
 struct ApplySlot {
     uint32_t *ldca;
     uint32_t *seav_w;

@@ -34,11 +34,6 @@ struct BatchTable {
     BatchDesc b[kMaxGroup];
     uint32_t n;
 };
-// Batches of a launch in device memory (any number), for the bucket-major kernels.
-struct BatchList {
-    const BatchDesc *b;
-    uint32_t n;
-};
 // Index of the batch that tile belongs to: the last one whose first tile is <= tile.
 __device__ __forceinline__ uint32_t find_batch(const BatchList &bl, uint32_t tile) {
     uint32_t lo = 0, hi = bl.n;   // b[lo].first_tile <= tile < b[hi].first_tile (b[n] = infinity)
@@ -48,6 +43,16 @@ __device__ __forceinline__ uint32_t find_batch(const BatchList &bl, uint32_t til
         else hi = mid;
     }
     return lo;
+}
+// The batch of a tile, from device memory or from the inline copies (constant indices only, so
+// that the kernel-argument array is never copied to scratch memory).
+__device__ __forceinline__ BatchDesc batch_of(const BatchList &bl, uint32_t tile) {
+    if (bl.b) return bl.b[find_batch(bl, tile)];
+    BatchDesc B = bl.inl[0];
+#pragma unroll
+    for (uint32_t i = 1; i < kInlineBatches; ++i)
+        if (i < bl.n && bl.inl[i].first_tile <= tile) B = bl.inl[i];
+    return B;
 }
 struct SlotTable {
     SlotPtrs s[kMaxGroup];
@@ -455,7 +460,7 @@ __global__ __launch_bounds__(BLOCK) void k_count(Consts c, BinGeometry g, BatchL
     uint32_t *samp = misc + 1;       // [2 * scap] sampled (hip, H2 bit)
     const uint32_t tid = threadIdx.x;
     const uint32_t tile = blockIdx.x;
-    const BatchDesc B = bl.b[find_batch(bl, tile)];
+    const BatchDesc B = bl.b[find_batch(bl, tile)];   // descriptors in device memory
     const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
     for (uint32_t i = tid; i < 2 * nb; i += BLOCK) hl[i] = 0;
     if (tid == 0) misc[0] = 0;
@@ -571,7 +576,7 @@ __global__ __launch_bounds__(BLOCK) void k_place(Consts c, BinGeometry g, BatchL
     uint32_t *samp = misc + 18;          // [2 * scap] sampled (hip, H2 bit)
     const uint32_t tid = threadIdx.x;
     const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
-    const BatchDesc B = bl.b[find_batch(bl, tile)];
+    const BatchDesc B = bl.b[find_batch(bl, tile)];   // descriptors in device memory
     const SlotPtrs S = st.s[B.slot];
     const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
 
@@ -770,7 +775,7 @@ __global__ __launch_bounds__(BLOCK) void k_region(Consts c, BinGeometry g, Batch
     uint32_t *misc = samp + 2 * g.scap;  // [0] sampled count, [1..17] scan scratch
     const uint32_t tid = threadIdx.x;
     const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
-    const BatchDesc B = bl.b[find_batch(bl, tile)];
+    const BatchDesc B = batch_of(bl, tile);
     const SlotPtrs S = st.s[B.slot];
     const uint64_t p0 = (uint64_t)(tile - B.first_tile) * (uint64_t)(PPT * BLOCK);
     const uint32_t cc = (tile - ct.lo[B.slot]) / kChunk, chunk = ct.cbase[B.slot] + cc;
@@ -909,11 +914,9 @@ static hipError_t launch_region_lr(const Consts &c, const BinGeometry &g, const 
     return hipGetLastError();
 }
 
-hipError_t launch_region(const Consts &c, const BinGeometry &g, const BatchDesc *batches_dev, uint32_t n_batches,
-                         uint32_t n_tiles, const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra,
-                         hipStream_t s) {
-    if (n_batches == 0 || n_tiles == 0) return hipErrorInvalidValue;
-    BatchList bl{batches_dev, n_batches};
+hipError_t launch_region(const Consts &c, const BinGeometry &g, const BatchList &bl, uint32_t n_tiles,
+                         const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra, hipStream_t s) {
+    if (bl.n == 0 || n_tiles == 0 || (!bl.b && bl.n > kInlineBatches)) return hipErrorInvalidValue;
     SlotTable st{};
     for (uint32_t i = 0; i < ct.n; ++i) st.s[i] = slots[i];
     switch (c.lr) {

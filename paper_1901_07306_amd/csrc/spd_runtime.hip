@@ -246,8 +246,9 @@ hipEvent_t prof_event(spd_ctx *ctx) {
         ctx->prof_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence (no cache writeback between the bracketed kernels)
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -577,9 +578,18 @@ spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<B
     ra.spill_n = ctx->aux + ctx->spill_parity;
     ra.spill_next = ctx->aux + (ctx->spill_parity ^ 1u);
     ra.cur = ctx->aux + 4;
-    BatchDesc *bdev = nullptr;
-    st = upload_batches(ctx, bd, s, &bdev);
-    if (st) return st;
+    // a few batches travel in the kernel arguments; more go through the pinned staging ring
+    BatchList bl{};
+    bl.n = (uint32_t)bd.size();
+    const bool inl = bd.size() <= kInlineBatches;
+    if (inl) {
+        std::copy(bd.begin(), bd.end(), bl.inl);
+    } else {
+        BatchDesc *bdev = nullptr;
+        st = upload_batches(ctx, bd, s, &bdev);
+        if (st) return st;
+        bl.b = bdev;
+    }
     {
         ProfScope ps(ctx, SPD_K_FILL, s);
         ClearList cl{};
@@ -601,10 +611,12 @@ spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<B
     ctx->aux_zero = false;   // until the launch's apply and spill phases are enqueued
     {
         ProfScope ps(ctx, SPD_K_BIN, s);
-        SPD_HIP(ctx, launch_region(ctx->c, g, bdev, (uint32_t)bd.size(), tiles, ct, sp, ra, s));
-        // the staging slot may be rewritten once the binning kernel has read it
-        SPD_HIP(ctx, hipEventRecord(ctx->bd_ev[ctx->bd_next], s));
-        ctx->bd_next = (ctx->bd_next + 1) % kBdRing;
+        SPD_HIP(ctx, launch_region(ctx->c, g, bl, tiles, ct, sp, ra, s));
+        if (!inl) {
+            // the staging slot may be rewritten once the binning kernel has read it
+            SPD_HIP(ctx, hipEventRecord(ctx->bd_ev[ctx->bd_next], s));
+            ctx->bd_next = (ctx->bd_next + 1) % kBdRing;
+        }
     }
     {
         ProfScope ps(ctx, SPD_K_APPLY, s);
