@@ -33,10 +33,15 @@ def log(*a):
 
 
 def kernel_source_sha() -> str:
+    """sha256[:16] of the kernel sources with comments, trailing blanks and blank lines removed:
+    a change of the code invalidates the committed counters, a change of a comment does not."""
+    import re
     h = hashlib.sha256()
     for f in ("spd_kernels.hip", "spd_internal.h"):
-        with open(os.path.join(ROOT, "paper_1901_07306_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1901_07306_amd", "csrc", f)) as fh:
+            src = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in src.split("\n")]
+        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

@@ -109,7 +109,7 @@ typedef struct spd_tuning {
     uint64_t launch_pairs;     /* binned scan: at most this many pairs per bin/apply launch (0: no limit);
                                   smaller launches keep their items resident in the Infinity Cache */
     uint32_t apply_unroll;     /* binned scan: tile segments each wavefront loads at once (8, 16, 32);
-                                  bucket-major layout: 4, 8 or 16 item words per lane */
+                                  region and exact-count layouts: 4, 8 or 16 item words per lane */
     uint32_t bin_mode;         /* binned scan layout: 0 = per-tile regions (one pass over the pairs);
                                   1 = bucket-major (an exact counting pass first, then contiguous
                                   per-bucket items that the apply phase streams);

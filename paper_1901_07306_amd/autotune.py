@@ -13,7 +13,7 @@ from typing import Dict, List, Optional, Tuple
 
 _CACHE: Dict[tuple, dict] = {}
 
-SCAN_KINDS = ("direct", "bin", "transpose", "apply", "fill", "count", "offsets")
+SCAN_KINDS = ("direct", "bin", "transpose", "apply", "fill", "count", "offsets", "spill")
 
 
 def _scan_ms(det, x, reps: int) -> float:
@@ -28,11 +28,12 @@ def _scan_ms(det, x, reps: int) -> float:
 
 def candidate_settings(quick: bool = False) -> List[dict]:
     if quick:
-        return [dict(bin_mode=1, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024, apply_unroll=16),
-                dict(bin_mode=1, bucket_bits=20, tile_pairs=16384, bin_block=1024, apply_block=1024, apply_unroll=16),
+        return [dict(bin_mode=2, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024, apply_unroll=16),
+                dict(bin_mode=2, bucket_bits=20, tile_pairs=8192, bin_block=512, apply_block=1024, apply_unroll=16),
+                dict(bin_mode=1, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024, apply_unroll=16),
                 dict(bin_mode=0, bucket_bits=20, tile_pairs=16384, bin_block=1024, apply_block=1024, apply_unroll=16)]
     out = []
-    for mode, S, T, bb, u in itertools.product((0, 1), (19, 20), (8192, 16384), (512, 1024), (8, 16)):
+    for mode, S, T, bb, u in itertools.product((0, 1, 2), (19, 20), (8192, 16384), (512, 1024), (8, 16)):
         out.append(dict(bin_mode=mode, bucket_bits=S, tile_pairs=T, bin_block=bb, apply_block=1024, apply_unroll=u))
     return out
 

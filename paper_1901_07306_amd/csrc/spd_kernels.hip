@@ -4,11 +4,14 @@
 // the SEAV.  Two kernels record a batch:
 //   * direct:  one thread per pair, global atomicOr per bit.  Device-wide random atomics run at a
 //              fixed rate on MI355X whatever the footprint, so this path serves small batches.
-//   * binned:  k_bin reads a tile of pairs, turns each pair into bit addresses, counting-sorts them
-//              in LDS by sketch bucket (2^S bits) and writes the tile's items bucket-major with
-//              coalesced stores; k_apply gives one workgroup per bucket, replays every tile's
-//              segment for that bucket into an LDS bitmap with LDS atomicOr, and writes the
-//              bucket back with plain stores.  No global atomics on the hot path.
+//   * binned:  a workgroup reads a tile of pairs, turns each pair into bit addresses and
+//              counting-sorts them in LDS by sketch bucket (2^S bits); an apply kernel gives one
+//              workgroup per bucket, replays the bucket's items into an LDS bitmap with LDS
+//              atomicOr, and writes the bucket back with plain stores.  No global atomics on the
+//              hot path.  Three item layouts: k_region writes each tile's segments into
+//              fixed-capacity (chunk of tiles, bucket) regions, read by k_apply_rg (the default,
+//              one pass over the pairs); k_count + k_place write one exact bucket-major stream,
+//              read by k_apply_bm; k_bin writes per-tile regions, gathered by k_apply.
 // End of window (Sections 3.2-3.3): k_close gives one wavefront per SEA (one RP): hot-SE lists
 // by ballot, the candidate product with Eq. 3 consistency and the SEU weight test, then the
 // ULDC of each candidate (AND over LR rows, popcount by wavefront reduction).

@@ -87,7 +87,7 @@ struct spd_ctx {
     uint64_t h2d_words = 0;             // per staging buffer
     hipStream_t h2d_s = nullptr;
     hipEvent_t h2d_copied[2] = {}, h2d_scanned[2] = {};
-    uint32_t *aux = nullptr;         // bucket-major layout: padded bucket totals and their prefix
+    uint32_t *aux = nullptr;         // region layout: counters; exact-count layout: bucket bases
     uint64_t aux_words = 0;
     bool aux_zero = false;           // region layout: every aux word is zero between launches
     uint32_t close_per_cu[3] = {0, 0, 0};   // resident end-of-window workgroups per CU (64, 128, 256 lanes)
@@ -686,7 +686,8 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
     const bool bm = ctx->tune.bin_mode != 0;
     for (Slot *sl : slots) {
         if (!sl->fresh) continue;
-        // bucket-major: the counting kernel clears a fresh slot's SEAV (before any bit reaches it)
+        // region and exact-count layouts: a fresh slot's SEAV is cleared inside the scan (the clear
+        // kernel or the counting kernel, before any bit reaches it)
         spd_status st = !binned ? clear_slot(ctx, *sl, s) : bm ? SPD_OK : clear_seav(ctx, *sl, s);
         if (st) return st;
         if (binned) fresh_slots.push_back(sl);
@@ -702,9 +703,8 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
         ws.swap(split);
     }
     // binned: launch groups of at most kMaxGroup slots and launch_pairs pairs; per-tile regions also
-    // take at most kMaxGroup batches per group, the bucket-major layout any number (its counting and
-    // placement kernels run over the group in chunks of kMaxGroup batches, its offsets and apply
-    // once per group, so each slot's buckets are read and written once per group)
+    // take at most kMaxGroup batches per group, the region and exact-count layouts any number (one
+    // launch of each kernel per group, so each slot's buckets are read and written once per group)
     size_t i0 = 0;
     while (i0 < ws.size()) {
         std::vector<BatchDesc> bd;

@@ -250,6 +250,13 @@ def test_error_paths():
         lib = spd.lib()
         st_ = lib.spd_scan(det.ctx, 0, x.data_ptr() + 4, 1, None)
         assert st_ == spd.SPD_E_INVALID
+        # tunings out of range are refused and leave the previous tuning in place
+        before = det.tuning.bin_mode
+        for bad in (dict(bin_mode=3), dict(region_words=(1 << 24) + 1), dict(apply_unroll=12)):
+            with pytest.raises(spd.SpdError) as e:
+                set_tuning(det, **bad)
+            assert e.value.status == spd.SPD_E_INVALID
+        assert det.tuning.bin_mode == before
     finally:
         det.close()
     # HBM budget: the sketches alone exceed it
@@ -391,6 +398,31 @@ def test_thousands_of_batches_one_call(layout):
         det.scan_batches([(int(o), x[a:a + len(p)]) for o, a, p in zip(owner, starts, parts)])
         for r in range(3):
             mine = np.concatenate([p for o, p in zip(owner, parts) if o == r])
+            ref = oracle_sketch(mp, mine)
+            assert_same_sketch(det, r, ref, f"router {r}")
+            assert_same_report(det.close_window(r), ref.detect(), f"router {r}")
+    finally:
+        det.close()
+
+
+@pytest.mark.parametrize("n_batches", [1, 8, 9, 40])
+def test_batches_inline_and_from_device_memory(n_batches):
+    """Up to 8 batches of a region launch travel in the kernel arguments, more in device memory:
+    both sides of the boundary, batches of two routers interleaved, equal the oracle."""
+    mp = PARAMS["plain_1m"]
+    rng = np.random.default_rng(97 + n_batches)
+    pairs, _ = heavy_hosts(rng, 4, 2500, noise=150_003)
+    cuts = np.sort(rng.choice(np.arange(1, len(pairs)), size=n_batches - 1, replace=False))
+    parts = np.split(pairs, cuts)
+    owner = [i % 2 for i in range(len(parts))]
+    log(f"case {n_batches} batches, region layout")
+    det = detector(mp, n_routers=2, **REGION)
+    try:
+        x = to_dev(pairs)
+        starts = np.concatenate([[0], cuts])
+        det.scan_batches([(o, x[a:a + len(p)]) for o, a, p in zip(owner, starts, parts)])
+        for r in range(2):
+            mine = np.concatenate([p for o, p in zip(owner, parts) if o == r] or [np.zeros((0, 2), np.uint32)])
             ref = oracle_sketch(mp, mine)
             assert_same_sketch(det, r, ref, f"router {r}")
             assert_same_report(det.close_window(r), ref.detect(), f"router {r}")
