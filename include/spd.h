@@ -139,8 +139,8 @@ typedef struct spd_stats {
 #define SPD_K_MERGE 5      /* router merge */
 #define SPD_K_CLOSE 6      /* end-of-window candidate rebuild and filter */
 #define SPD_K_FILL 7       /* clears (window reset, counters) */
-#define SPD_K_COUNT 8      /* bucket-major binned scan: exact per-tile counts */
-#define SPD_K_OFFSETS 9    /* bucket-major binned scan: per-tile segment offsets */
+#define SPD_K_COUNT 8      /* exact-count layout (bin_mode 1): per-tile bucket counts */
+#define SPD_K_OFFSETS 9    /* exact-count layout (bin_mode 1): per-tile segment offsets */
 #define SPD_K_SPILL 10     /* region layout: words past a region's capacity */
 #define SPD_K_KINDS 11
 
