@@ -694,12 +694,19 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
         sl->fresh = false;
     }
     if (!binned) return direct_launch(false);
-    // split batches larger than one launch may take
+    // split batches larger than one launch may take: launch_pairs, and for the region and
+    // exact-count layouts the 32-bit item offsets of one launch (tiles * cap < 2^32)
     const uint64_t lp = ctx->tune.launch_pairs;
-    if (lp) {
+    uint64_t split_at = lp;
+    if (bm) {
+        const uint64_t max_pairs = (((1ull << 32) - 1) / g.cap - 1) * g.tile_pairs;
+        split_at = split_at ? std::min(split_at, max_pairs) : max_pairs;
+    }
+    if (split_at) {
         std::vector<WorkItem> split;
         for (auto &w : ws)
-            for (uint64_t a = 0; a < w.n; a += lp) split.push_back(WorkItem{w.slot, w.pairs + 2 * a, std::min(lp, w.n - a), w.swap});
+            for (uint64_t a = 0; a < w.n; a += split_at)
+                split.push_back(WorkItem{w.slot, w.pairs + 2 * a, std::min(split_at, w.n - a), w.swap});
         ws.swap(split);
     }
     // binned: launch groups of at most kMaxGroup slots and launch_pairs pairs; per-tile regions also
@@ -718,6 +725,9 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             const WorkItem &w = ws[i];
             if (w.n == 0) continue;
             if (lp && !bd.empty() && lpairs + w.n > lp) break;
+            const uint64_t nt = (w.n + g.tile_pairs - 1) / g.tile_pairs;
+            // a group ends before its item offsets would pass 32 bits
+            if (bm && !bd.empty() && ((uint64_t)tiles + nt) * g.cap >= (1ull << 32)) break;
             lpairs += w.n;
             if (nsl == 0 || owner[nsl - 1] != w.slot) {
                 if (nsl == (uint32_t)kMaxGroup) break;
@@ -730,7 +740,6 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                 owner[nsl] = w.slot;
                 ++nsl;
             }
-            const uint64_t nt = (w.n + g.tile_pairs - 1) / g.tile_pairs;
             if ((uint64_t)tiles + nt > 0x7FFFFFFFull) return fail(ctx, SPD_E_INVALID, "batch too large");
             bd.push_back(BatchDesc{w.pairs, w.n, tiles, nsl - 1, w.swap, 0});
             tiles += (uint32_t)nt;

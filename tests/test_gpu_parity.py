@@ -430,6 +430,32 @@ def test_batches_inline_and_from_device_memory(n_batches):
         det.close()
 
 
+def test_scan_larger_than_one_launch():
+    """A call over more pairs than one launch's 32-bit item offsets allow (about 1.79 Gi pairs at
+    plain_64m sizes) is split into launches; the sketch is a function of the set of pairs, so it
+    equals the sketch of the same pairs scanned in four calls (far too many pairs for the oracle)."""
+    mp = st.CONFIGS["plain_64m"].params
+    n = 2 << 30
+    gen = torch.Generator(device="cuda").manual_seed(2024)
+    x = torch.randint(-(1 << 31), (1 << 31) - 1, (n, 2), dtype=torch.int32, device="cuda", generator=gen)
+    log(f"case {n} pairs in one call")
+    one, four = detector(mp, **REGION), detector(mp, **REGION)
+    try:
+        one.scan(0, x)
+        for k in range(4):
+            four.scan(0, x[k * (n // 4):(k + 1) * (n // 4)])
+        torch.cuda.synchronize()
+        assert one.stats.binned_launches >= 2
+        a, b = one.export(0), four.export(0)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert a[1].any()
+    finally:
+        one.close()
+        four.close()
+        del x
+        torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------------------------------ both directions
 @pytest.mark.parametrize("mode", ["direct", "binned_small", "binned_default", "bucket_major_small", "region_spill"])
 def test_both_directions_one_call(mode):
