@@ -24,6 +24,7 @@ struct Slot {
     uint16_t *ldca_ts = nullptr;
     uint16_t *seav_ts = nullptr;
     bool fresh = true;           // logically all zero; device memory not yet cleared
+    bool seav_zero = false;      // fresh, and its SEAV already zeroed (after the close that reset it)
 };
 
 struct WorkItem {
@@ -340,6 +341,7 @@ spd_status clear_slot(spd_ctx *ctx, Slot &s, hipStream_t st) {
         SPD_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(s.mem), slot_words(ctx), 0u, st));
     }
     s.fresh = false;
+    s.seav_zero = false;
     return SPD_OK;
 }
 
@@ -563,7 +565,8 @@ spd_status ensure_scratch(spd_ctx *ctx, uint64_t items_words, uint64_t meta_word
 // apply every (slot, bucket), then the spill list.  SPD_E_NOMEM (nothing enqueued) if its scratch
 // does not fit the HBM budget.
 spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<BatchDesc> &bd, uint32_t tiles,
-                         const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, uint32_t nsl, hipStream_t s) {
+                         const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, const bool *seav_clean,
+                         uint32_t nsl, hipStream_t s) {
     RegionArgs ra{};
     uint64_t items_words = 0, cur_words = 0;
     region_layout(ctx, g, ct, tiles, &ra, &items_words, &cur_words);
@@ -598,7 +601,7 @@ spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<B
             cl.words[cl.n++] = ctx->aux_words;
         }
         for (uint32_t k = 0; k < nsl; ++k) {
-            if (!as[k].fresh) continue;
+            if (!as[k].fresh || seav_clean[k]) continue;
             if (cl.n == (uint32_t)kMaxGroup) {
                 SPD_HIP(ctx, launch_clear(cl, s));
                 cl.n = 0;
@@ -682,13 +685,16 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
     if (ctx->sliding) return direct_launch(true);   // time stamps of the current slice, plain stores
     BinGeometry g{};
     const bool binned = total > ctx->tune.direct_max_pairs && ctx->p.lr <= 4 && bin_geometry(ctx, &g);
-    std::vector<Slot *> fresh_slots;
+    std::vector<Slot *> fresh_slots, clean_slots;
     const bool bm = ctx->tune.bin_mode != 0;
     for (Slot *sl : slots) {
         if (!sl->fresh) continue;
+        const bool clean = sl->seav_zero && binned;   // its SEAV needs no clear in this scan
+        if (clean) clean_slots.push_back(sl);
+        sl->seav_zero = false;
         // region and exact-count layouts: a fresh slot's SEAV is cleared inside the scan (the clear
         // kernel or the counting kernel, before any bit reaches it)
-        spd_status st = !binned ? clear_slot(ctx, *sl, s) : bm ? SPD_OK : clear_seav(ctx, *sl, s);
+        spd_status st = !binned ? clear_slot(ctx, *sl, s) : (bm || clean) ? SPD_OK : clear_seav(ctx, *sl, s);
         if (st) return st;
         if (binned) fresh_slots.push_back(sl);
         sl->fresh = false;
@@ -717,6 +723,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
         std::vector<BatchDesc> bd;
         SlotPtrs sp[kMaxGroup] = {};
         ApplySlot as[kMaxGroup] = {};
+        bool seav_clean[kMaxGroup] = {};   // fresh slots whose SEAV is already zero
         Slot *owner[kMaxGroup] = {};
         uint32_t nsl = 0, tiles = 0;
         uint64_t lpairs = 0;
@@ -737,6 +744,8 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                 as[nsl].tile_lo = tiles;
                 // a fresh slot's LDCA buckets are written from zero by this launch
                 as[nsl].fresh = std::find(fresh_slots.begin(), fresh_slots.end(), w.slot) != fresh_slots.end();
+                seav_clean[nsl] = as[nsl].fresh &&
+                                  std::find(clean_slots.begin(), clean_slots.end(), w.slot) != clean_slots.end();
                 owner[nsl] = w.slot;
                 ++nsl;
             }
@@ -780,7 +789,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             const uint32_t chunks = ct.cbase[nsl];
             if (ctx->tune.bin_mode == 2) {
                 // the exact-count layout (less scratch) if the region layout does not fit the budget
-                spd_status st = region_launch(ctx, g, bd, tiles, ct, sp, as, nsl, s);
+                spd_status st = region_launch(ctx, g, bd, tiles, ct, sp, as, seav_clean, nsl, s);
                 if (st && st != SPD_E_NOMEM) return st;
                 if (!st) {
                     for (uint32_t k = 0; k < nsl; ++k)
@@ -801,7 +810,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             if (st) return st;
             ClearList cl{};
             for (uint32_t k = 0; k < nsl; ++k)
-                if (as[k].fresh) {
+                if (as[k].fresh && !seav_clean[k]) {
                     cl.p[cl.n] = as[k].seav_w;
                     cl.words[cl.n++] = ctx->seav_alloc / 4;
                 }
@@ -1256,6 +1265,7 @@ spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *st
     if (live.empty()) {
         if (ctx->sliding) return clear_slot(ctx, g, s);
         g.fresh = true;
+        g.seav_zero = false;
         return SPD_OK;
     }
     const uint64_t words = slot_words(ctx);
@@ -1275,6 +1285,7 @@ spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *st
         }
     }
     g.fresh = false;
+    g.seav_zero = false;
     return SPD_OK;
 }
 
@@ -1294,6 +1305,13 @@ spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_ho
     SPD_HIP(ctx, hipStreamSynchronize(s));
     st = close_finish(ctx, *sl, ctx->cbuf, s, &res);
     if (st) return st;
+    if (!ctx->sliding && !ctx->cbuf.empty) {
+        // the window is reported (no re-run can need it): zero its SEAV now, while the host builds
+        // the report and submits the next scan, instead of at the start of that scan
+        ProfScope ps(ctx, SPD_K_FILL, s);
+        SPD_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sl->seav), ctx->seav_alloc / 4, 0u, s));
+        sl->seav_zero = true;
+    }
     const uint32_t n = (uint32_t)res.size();
     const uint32_t w = std::min(n, cap);
     if (w) std::memcpy(out_host, res.data(), (size_t)w * sizeof(spd_superpoint));
