@@ -685,21 +685,27 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
     if (ctx->sliding) return direct_launch(true);   // time stamps of the current slice, plain stores
     BinGeometry g{};
     const bool binned = total > ctx->tune.direct_max_pairs && ctx->p.lr <= 4 && bin_geometry(ctx, &g);
-    std::vector<Slot *> fresh_slots, clean_slots;
     const bool bm = ctx->tune.bin_mode != 0;
-    for (Slot *sl : slots) {
-        if (!sl->fresh) continue;
-        const bool clean = sl->seav_zero && binned;   // its SEAV needs no clear in this scan
-        if (clean) clean_slots.push_back(sl);
-        sl->seav_zero = false;
-        // region and exact-count layouts: a fresh slot's SEAV is cleared inside the scan (the clear
-        // kernel or the counting kernel, before any bit reaches it)
-        spd_status st = !binned ? clear_slot(ctx, *sl, s) : (bm || clean) ? SPD_OK : clear_seav(ctx, *sl, s);
-        if (st) return st;
-        if (binned) fresh_slots.push_back(sl);
-        sl->fresh = false;
+    if (!binned) {
+        for (Slot *sl : slots)
+            if (sl->fresh) {
+                spd_status st = clear_slot(ctx, *sl, s);
+                if (st) return st;
+            }
+        return direct_launch(false);
     }
-    if (!binned) return direct_launch(false);
+    // Binned: a slot's flags change only once a group covering it has been enqueued, so that an
+    // error return (a budget refusal before anything was enqueued) leaves every slot as it was.
+    // A fresh slot's LDCA buckets are written from zero by the apply phase; its SEAV is cleared
+    // inside the scan (the clear kernel, the counting kernel, or a fill before the per-tile
+    // binning), unless the close that reset it has already zeroed it (seav_zero).
+    // later groups of the same call OR into the slots an enqueued group has written
+    auto mark_written = [](Slot *const *owner, uint32_t n) {
+        for (uint32_t k = 0; k < n; ++k) {
+            owner[k]->fresh = false;
+            owner[k]->seav_zero = false;
+        }
+    };
     // split batches larger than one launch may take: launch_pairs, and for the region and
     // exact-count layouts the 32-bit item offsets of one launch (tiles * cap < 2^32)
     const uint64_t lp = ctx->tune.launch_pairs;
@@ -743,9 +749,8 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                 as[nsl].seav_w = reinterpret_cast<uint32_t *>(w.slot->seav);
                 as[nsl].tile_lo = tiles;
                 // a fresh slot's LDCA buckets are written from zero by this launch
-                as[nsl].fresh = std::find(fresh_slots.begin(), fresh_slots.end(), w.slot) != fresh_slots.end();
-                seav_clean[nsl] = as[nsl].fresh &&
-                                  std::find(clean_slots.begin(), clean_slots.end(), w.slot) != clean_slots.end();
+                as[nsl].fresh = w.slot->fresh ? 1u : 0u;
+                seav_clean[nsl] = w.slot->fresh && w.slot->seav_zero;
                 owner[nsl] = w.slot;
                 ++nsl;
             }
@@ -762,6 +767,11 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
         if (ctx->tune.bin_mode == 0) {
             spd_status st = ensure_scratch(ctx, items_words, meta_words, s);
             if (st) return st;
+            for (uint32_t k = 0; k < nsl; ++k)   // SEAV bits may be recorded directly by the binning
+                if (as[k].fresh && !seav_clean[k]) {
+                    st = clear_seav(ctx, *owner[k], s);
+                    if (st) return st;
+                }
             {
                 ProfScope ps(ctx, SPD_K_BIN, s);
                 SPD_HIP(ctx, launch_bin(ctx->c, g, bd.data(), nbd, tiles, ctx->items, ctx->meta, sp, s));
@@ -792,9 +802,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                 spd_status st = region_launch(ctx, g, bd, tiles, ct, sp, as, seav_clean, nsl, s);
                 if (st && st != SPD_E_NOMEM) return st;
                 if (!st) {
-                    for (uint32_t k = 0; k < nsl; ++k)
-                        fresh_slots.erase(std::remove(fresh_slots.begin(), fresh_slots.end(), owner[k]),
-                                          fresh_slots.end());
+                    mark_written(owner, nsl);
                     ctx->stats.binned_launches++;
                     continue;
                 }
@@ -835,9 +843,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                 SPD_HIP(ctx, launch_apply_bm(g, as, nsl, ctx->items, base, ctx->tune.apply_block, ctx->tune.apply_unroll, s));
             }
         }
-        // later groups of the same call OR into these slots
-        for (uint32_t k = 0; k < nsl; ++k)
-            fresh_slots.erase(std::remove(fresh_slots.begin(), fresh_slots.end(), owner[k]), fresh_slots.end());
+        mark_written(owner, nsl);
         ctx->stats.binned_launches++;
     }
     ctx->stats.pairs_scanned += total;

@@ -299,20 +299,28 @@ def gen_routers(w: Workload, seed: Optional[int] = None) -> Window:
     p_owner = np.repeat(np.arange(w.n_planted), cards)
     p_router = p_perm[p_owner, (rng.random(p_owner.size) * p_size[p_owner]).astype(np.int64)]
     n_distinct = w.n_packets - int(round(w.dup_frac * w.n_packets))
-    out = []
-    kept_all = np.zeros(w.n_sources, dtype=np.int64)
-    for r in range(R):
+    # the background slots of each router, ascending (a stable sort groups them by router)
+    by_router = np.argsort(slot_router, kind="stable")
+    bounds = np.searchsorted(slot_router[by_router], np.arange(R + 1))
+
+    def one_router(r):
         rr = rng_for(seed, 1, r)
         ps, pd = p_src[p_router == r], p_dst[p_router == r]
-        mine = np.nonzero(slot_router == r)[0]
+        mine = by_router[bounds[r]:bounds[r + 1]]
         need = n_distinct - ps.size
         assert 0 < need <= mine.size, (need, mine.size)
         mine = mine[subset(rr, mine.size, need)]
         s_idx = slots[mine]
-        kept_all += np.bincount(s_idx, minlength=w.n_sources)
         src = np.concatenate([ps, bg[s_idx]])
         dst = np.concatenate([pd, random_u32(rr, s_idx.size)])
-        out.append(_finish(rr, src, dst, w.n_packets))
+        return _finish(rr, src, dst, w.n_packets), np.bincount(s_idx, minlength=w.n_sources)
+
+    # every router draws from its own generator, so the threads give the same output in any order
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(R, 8)) as ex:
+        done = list(ex.map(one_router, range(R)))
+    out = [d[0] for d in done]
+    kept_all = np.sum([d[1] for d in done], axis=0)
     return Window(out, planted, cards.astype(np.int64), int(kept_all.max()))
 
 
@@ -351,7 +359,8 @@ class SlidingTraffic:
         active = np.nonzero((self.on <= t) & (t < self.off))[0]
         n_pl = int(self.rate[active].sum())
         n_bg = w.n_packets - n_pl
-        s = np.searchsorted(self.cdf, rng.random(n_bg), side="right")
+        # sorted draws make the search sequential; the final permutation shuffles the pairs anyway
+        s = np.searchsorted(self.cdf, np.sort(rng.random(n_bg)), side="right")
         j = (rng.random(n_bg) * self.counts[s]).astype(np.int64)
         bsrc = self.src_ips[s]
         bdst = _peer_ip(bsrc, j, self.seed)

@@ -7,6 +7,8 @@ count the binned kernel supports, router merges, window resets, import/export, e
 saturated SEAs (the brute-force branch of the end-of-window kernel), the sliding window, and the
 full-size 1,000,000-pair and 64 Mi-pair windows.
 """
+import zlib
+
 import numpy as np
 import pytest
 
@@ -56,22 +58,35 @@ PARAMS = {
     "lr1_sr2": st.MethodParams(theta=1024, r=10, sr=2, a=3, log2k=12, lr=1, log2lc=10, hash_seed=11),
     "lr3_sr5": st.MethodParams(theta=512, r=12, sr=5, a=2, log2k=11, lr=3, log2lc=9, hash_seed=13),
     "lr4_sr4": st.MethodParams(theta=2048, r=8, sr=4, a=2, log2k=13, lr=4, log2lc=7, hash_seed=17),
+    # a 32 KiB SEAV: small enough for the direct kernel's per-workgroup LDS copy
+    "seav_32k": st.MethodParams(theta=1024, r=4, sr=4, a=2, log2k=12, lr=2, log2lc=10, hash_seed=19),
 }
 
 
 MODES = {"direct": DIRECT, "binned_small": BINNED_SMALL, "binned_default": BINNED_DEFAULT,
          "binned_chunked": BINNED_CHUNKED, "bucket_major": BUCKET_MAJOR, "bucket_major_small": BUCKET_MAJOR_SMALL,
          "bucket_major_wide": BUCKET_MAJOR_WIDE, "region": REGION, "region_small": REGION_SMALL,
-         "region_spill": REGION_SPILL, "region_spill_all": REGION_SPILL_ALL}
+         "region_spill": REGION_SPILL, "region_spill_all": REGION_SPILL_ALL,
+         # the direct kernel's per-workgroup LDS copy of the SEAV (taken when the SEAV is at most 64 KiB)
+         "direct_seav_lds": dict(DIRECT, seav_lds=1),
+         # end-of-window workgroups of one and two wavefronts
+         "direct_close64": dict(DIRECT, close_block=64),
+         "region_close128": dict(REGION, close_block=128)}
+
+
+def seed_of(*names) -> int:
+    """A fixed seed per test case (CRC-32 of its name), the same in every process."""
+    return zlib.crc32("/".join(names).encode())
 
 
 @pytest.mark.parametrize("pname", list(PARAMS))
 @pytest.mark.parametrize("mode", list(MODES))
 def test_scan_and_close_parity(pname, mode):
     mp = PARAMS[pname]
-    log(f"case params={pname} mode={mode}")
+    seed = seed_of(pname, mode)
+    log(f"case params={pname} mode={mode} seed={seed}")
     tune = MODES[mode]
-    rng = np.random.default_rng(hash((pname, mode)) % (1 << 32))
+    rng = np.random.default_rng(seed)
     heavy, _ = heavy_hosts(rng, 8, 3000, noise=150_001)   # ragged: not a multiple of any tile
     det = detector(mp, **tune)
     try:
