@@ -180,6 +180,22 @@ spd_status spd_scan(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_dev, ui
 spd_status spd_scan_host(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_host, uint64_t n_pairs, uint32_t flags,
                          uint64_t chunk_pairs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): spd_scan without any allocation.  Same result as
+ * spd_scan.  flags: 0 or SPD_BATCH_DST.  Discrete-window contexts only (SPD_E_STATE otherwise).
+ * Batches up to the tuning's direct_max_pairs take the direct kernel, which needs no scratch;
+ * larger ones take the region layout of the binned scan with all of its scratch in one fixed array
+ * of SPD_NOALLOC_SCRATCH_BYTES device bytes that the library holds on every GPU it runs on until
+ * the process ends, in as many launches as that array requires (each launch reads and writes the
+ * whole sketch, so this is slower than spd_scan for large batches).  SPD_E_INVALID if one tile of
+ * the sketch geometry alone needs more scratch than the array.  No timing events are recorded.
+ * Every no-alloc call on one GPU shares that GPU's array, from any context: calls whose work may
+ * overlap on the device (different streams, no ordering between them) race and must be ordered
+ * by the caller.  Each call clears the counters it needs before use. */
+#define SPD_NOALLOC_SCRATCH_BYTES (64u << 20)
+spd_status spd_scan_noalloc(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_dev, uint64_t n_pairs, uint32_t flags,
+                            void *stream);
+
 /* Record several batches, from any routers and of any sizes, in one fused pass (same result as
  * calling spd_scan on each batch). */
 spd_status spd_scan_batches(spd_ctx *ctx, const spd_batch *batches, uint32_t n_batches, void *stream);

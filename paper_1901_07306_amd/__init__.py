@@ -88,7 +88,7 @@ class SpdServerStats(ctypes.Structure):
 
 RECORD = np.dtype([("ip", "<u4"), ("z0", "<u4"), ("est", "<u4"), ("flags", "<u4")])
 
-EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_host", "spd_scan_batches", "spd_merge",
+EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_noalloc", "spd_scan_host", "spd_scan_batches", "spd_merge",
             "spd_close_window", "spd_slide", "spd_export", "spd_import", "spd_export_stamps",
             "spd_current_slice", "spd_get_tuning", "spd_set_tuning", "spd_get_stats", "spd_strerror",
             "spd_last_error", "spd_profile_enable", "spd_profile_select", "spd_get_profile", "spd_server_create", "spd_server_submit",
@@ -144,6 +144,7 @@ def lib(require_torch: bool = True) -> ctypes.CDLL:
         "spd_destroy": (None, [vp]),
         "spd_scan": (i32, [vp, u32, vp, u64, vp]),
         "spd_scan_host": (i32, [vp, u32, vp, u64, u32, u64, vp]),
+        "spd_scan_noalloc": (i32, [vp, u32, vp, u64, u32, vp]),
         "spd_scan_batches": (i32, [vp, P(SpdBatch), u32, vp]),
         "spd_merge": (i32, [vp, P(u32), u32, vp]),
         "spd_close_window": (i32, [vp, i32, P(SpdSuperpoint), u32, P(u32), vp]),
@@ -249,6 +250,13 @@ def spd_scan(ctx: int, router: int, pairs, stream=None) -> None:
 
 
 BATCH_DST = 1   # destination-keyed batch: records read as (oip, hip)
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SPD_NOALLOC_SCRATCH_BYTES
+
+
+def spd_scan_noalloc(ctx: int, router: int, pairs, flags: int = 0, stream=None) -> None:
+    """spd_scan that allocates nothing (scratch in the library's fixed per-GPU array)."""
+    ptr, n = _pairs_ptr(pairs)
+    _check(lib().spd_scan_noalloc(ctx, router, ptr or None, n, flags, _stream_ptr(stream)), ctx)
 
 
 def _host_pairs_ptr(pairs) -> Tuple[int, int, object]:
@@ -385,6 +393,9 @@ class Detector:
 
     def scan(self, router, pairs, stream=None):
         spd_scan(self.ctx, router, pairs, stream)
+
+    def scan_noalloc(self, router, pairs, flags=0, stream=None):
+        spd_scan_noalloc(self.ctx, router, pairs, flags, stream)
 
     def scan_host(self, router, pairs, flags=0, chunk_pairs=0, stream=None):
         """Pairs in host memory (numpy array or CPU tensor), copied in chunks overlapping the scan."""

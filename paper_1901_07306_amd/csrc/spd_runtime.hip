@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -97,6 +98,8 @@ struct spd_ctx {
     uint32_t *view = nullptr;       // sliding export: bit view words
     uint64_t view_words = 0;
     std::vector<uint32_t> est;      // Eq. 4 estimate for every z0 in [0, k]
+    uint8_t *noalloc = nullptr;     // device address of this device's no-alloc scratch array
+    std::string noalloc_err;        // why it is missing (lookup failed at creation)
     spd_tuning tune{};
     spd_stats stats{};
     std::string err;
@@ -115,7 +118,32 @@ struct spd_ctx {
     spd_profile prof{};
 };
 
+// Scratch of spd_scan_noalloc: a fixed array in device memory.  Every GPU the library runs on
+// holds its own copy, at its own address, until the process ends.  In host code the name is only
+// a stand-in for the device symbol and is never passed to a kernel: host code uses the device
+// address that hipGetSymbolAddress returns on each device (noalloc_lookup), kept per device.
+static __device__ __align__(256) uint8_t scratch[SPD_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+uint8_t *g_noalloc_addr[kMaxDevices] = {};   // per device: the address of `scratch`, once looked up
+
+// The device address of `scratch` on `device`, which must be the current device.
+hipError_t noalloc_lookup(int device, uint8_t **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_addr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_noalloc_addr[device] = static_cast<uint8_t *>(ptr);
+    }
+    *out = g_noalloc_addr[device];
+    return hipSuccess;
+}
 
 struct DeviceGuard {
     int prev = -1;
@@ -425,13 +453,13 @@ spd_status ensure_batch_ring(spd_ctx *ctx, size_t n) {
     return SPD_OK;
 }
 
-spd_status upload_batches(spd_ctx *ctx, const std::vector<BatchDesc> &bd, hipStream_t s, BatchDesc **out) {
-    spd_status st = ensure_batch_ring(ctx, bd.size());
+spd_status upload_batches(spd_ctx *ctx, const BatchDesc *bd, size_t n, hipStream_t s, BatchDesc **out) {
+    spd_status st = ensure_batch_ring(ctx, n);
     if (st) return st;
     const uint32_t k = ctx->bd_next;
     SPD_HIP(ctx, hipEventSynchronize(ctx->bd_ev[k]));
-    std::memcpy(ctx->bd_host[k], bd.data(), bd.size() * sizeof(BatchDesc));
-    SPD_HIP(ctx, hipMemcpyAsync(ctx->bd_dev[k], ctx->bd_host[k], bd.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+    std::memcpy(ctx->bd_host[k], bd, n * sizeof(BatchDesc));
+    SPD_HIP(ctx, hipMemcpyAsync(ctx->bd_dev[k], ctx->bd_host[k], n * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
     *out = ctx->bd_dev[k];
     return SPD_OK;
 }
@@ -561,44 +589,56 @@ spd_status ensure_scratch(spd_ctx *ctx, uint64_t items_words, uint64_t meta_word
     return SPD_OK;
 }
 
-// One group of the region layout: clear (fresh SEAVs, region counters), bin into the regions,
-// apply every (slot, bucket), then the spill list.  SPD_E_NOMEM (nothing enqueued) if its scratch
-// does not fit the HBM budget.
-spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<BatchDesc> &bd, uint32_t tiles,
-                         const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, const bool *seav_clean,
-                         uint32_t nsl, hipStream_t s) {
+// Scratch of one region-layout group: the item regions and spill list (`items`), the spill counts
+// and region counters (`aux`), whether every aux word is known to be zero, and which of the two
+// spill counts the group uses.
+struct RegionScratch {
+    uint32_t *items;
+    uint64_t items_words;
+    uint32_t *aux;
+    uint64_t aux_words;
+    bool *aux_zero;
+    uint32_t *parity;
+};
+
+// One group of the region layout in the given scratch: clear (fresh SEAVs, region counters), bin
+// into the regions, apply every (slot, bucket), then the spill list.  SPD_E_INVALID (nothing
+// enqueued) if the group's layout does not fit the scratch.
+spd_status region_launch_at(spd_ctx *ctx, const BinGeometry &g, const BatchDesc *bd, uint32_t nbd, uint32_t tiles,
+                            const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, const bool *seav_clean,
+                            uint32_t nsl, const RegionScratch &rs, hipStream_t s) {
     RegionArgs ra{};
     uint64_t items_words = 0, cur_words = 0;
     region_layout(ctx, g, ct, tiles, &ra, &items_words, &cur_words);
     if (ra.chunk_words >= (1ull << 31)) return fail(ctx, SPD_E_INVALID, "region layout: chunk too large");
-    spd_status st = ensure_scratch(ctx, items_words, 0, s);
-    if (!st) st = ensure_aux(ctx, cur_words, s);
-    if (st) return st;
+    if (items_words > rs.items_words || cur_words > rs.aux_words)
+        return fail(ctx, SPD_E_INVALID, "region layout larger than its scratch");
     const uint64_t region_words = items_words - (uint64_t)ra.spill_cap * 3;   // 32-bit words
-    ra.items = reinterpret_cast<uint64_t *>(ctx->items);
-    ra.spill_w = reinterpret_cast<uint64_t *>(ctx->items + region_words);
-    ra.spill_tag = ctx->items + region_words + (uint64_t)ra.spill_cap * 2;
-    ra.spill_n = ctx->aux + ctx->spill_parity;
-    ra.spill_next = ctx->aux + (ctx->spill_parity ^ 1u);
-    ra.cur = ctx->aux + 4;
+    const uint32_t par = *rs.parity;
+    ra.items = reinterpret_cast<uint64_t *>(rs.items);
+    ra.spill_w = reinterpret_cast<uint64_t *>(rs.items + region_words);
+    ra.spill_tag = rs.items + region_words + (uint64_t)ra.spill_cap * 2;
+    ra.spill_n = rs.aux + par;
+    ra.spill_next = rs.aux + (par ^ 1u);
+    ra.cur = rs.aux + 4;
     // a few batches travel in the kernel arguments; more go through the pinned staging ring
     BatchList bl{};
-    bl.n = (uint32_t)bd.size();
-    const bool inl = bd.size() <= kInlineBatches;
+    bl.n = nbd;
+    const bool inl = nbd <= kInlineBatches;
     if (inl) {
-        std::copy(bd.begin(), bd.end(), bl.inl);
+        std::copy(bd, bd + nbd, bl.inl);
     } else {
         BatchDesc *bdev = nullptr;
-        st = upload_batches(ctx, bd, s, &bdev);
+        spd_status st = upload_batches(ctx, bd, nbd, s, &bdev);
         if (st) return st;
         bl.b = bdev;
     }
     {
         ProfScope ps(ctx, SPD_K_FILL, s);
         ClearList cl{};
-        if (!ctx->aux_zero) {   // after (re)allocation, another layout's use, or a failed launch
-            cl.p[cl.n] = ctx->aux;
-            cl.words[cl.n++] = ctx->aux_words;
+        if (!*rs.aux_zero) {   // after (re)allocation, another layout's use, or a failed launch
+            cl.p[cl.n] = rs.aux;
+            cl.words[cl.n++] = rs.aux_words;
         }
         for (uint32_t k = 0; k < nsl; ++k) {
             if (!as[k].fresh || seav_clean[k]) continue;
@@ -611,7 +651,7 @@ spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<B
         }
         SPD_HIP(ctx, launch_clear(cl, s));
     }
-    ctx->aux_zero = false;   // until the launch's apply and spill phases are enqueued
+    *rs.aux_zero = false;   // until the launch's apply and spill phases are enqueued
     {
         ProfScope ps(ctx, SPD_K_BIN, s);
         SPD_HIP(ctx, launch_region(ctx->c, g, bl, tiles, ct, sp, ra, s));
@@ -629,9 +669,25 @@ spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<B
         ProfScope ps(ctx, SPD_K_SPILL, s);
         SPD_HIP(ctx, launch_spill(g, as, nsl, ra, s));
     }
-    ctx->spill_parity ^= 1u;
-    ctx->aux_zero = true;
+    *rs.parity = par ^ 1u;
+    *rs.aux_zero = true;
     return SPD_OK;
+}
+
+// The same in the context's scratch, grown on demand within the HBM budget: SPD_E_NOMEM (nothing
+// enqueued) if it does not fit.
+spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<BatchDesc> &bd, uint32_t tiles,
+                         const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, const bool *seav_clean,
+                         uint32_t nsl, hipStream_t s) {
+    RegionArgs ra{};
+    uint64_t items_words = 0, cur_words = 0;
+    region_layout(ctx, g, ct, tiles, &ra, &items_words, &cur_words);
+    if (ra.chunk_words >= (1ull << 31)) return fail(ctx, SPD_E_INVALID, "region layout: chunk too large");
+    spd_status st = ensure_scratch(ctx, items_words, 0, s);
+    if (!st) st = ensure_aux(ctx, cur_words, s);
+    if (st) return st;
+    const RegionScratch rs{ctx->items, ctx->items_words, ctx->aux, ctx->aux_words, &ctx->aux_zero, &ctx->spill_parity};
+    return region_launch_at(ctx, g, bd.data(), (uint32_t)bd.size(), tiles, ct, sp, as, seav_clean, nsl, rs, s);
 }
 
 // Record batches into slots.  Batches of one slot are kept together so that each slot's tiles are
@@ -814,7 +870,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             ctx->aux_zero = false;
             // the batch descriptors go to device memory through a pinned staging ring
             BatchDesc *bdev = nullptr;
-            st = upload_batches(ctx, bd, s, &bdev);
+            st = upload_batches(ctx, bd.data(), bd.size(), s, &bdev);
             if (st) return st;
             ClearList cl{};
             for (uint32_t k = 0; k < nsl; ++k)
@@ -847,6 +903,90 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
         ctx->stats.binned_launches++;
     }
     ctx->stats.pairs_scanned += total;
+    return SPD_OK;
+}
+
+// Scan of one batch into one slot with no allocation: the direct kernel for small batches (no
+// scratch), else the region layout with its scratch in the no-alloc array, in launches of as many
+// tiles as that array holds.  No timing events, no descriptor ring (one inline batch per launch).
+spd_status scan_noalloc(spd_ctx *ctx, Slot *sl, const uint32_t *pairs, uint64_t n, uint32_t swap, hipStream_t s) {
+    BinGeometry g{};
+    const bool binned = n > ctx->tune.direct_max_pairs && ctx->p.lr <= 4 && bin_geometry(ctx, &g);
+    if (!binned) {
+        if (sl->fresh) {
+            spd_status st = clear_slot(ctx, *sl, s);
+            if (st) return st;
+        }
+        BatchDesc bd[1] = {BatchDesc{pairs, n, 0, 0, swap, 0}};
+        SlotPtrs sp[kMaxGroup] = {};
+        sp[0] = ptrs_of(*sl);
+        const uint32_t block = ctx->tune.direct_block;
+        const uint64_t want = (n + block - 1) / block;
+        const uint32_t grid = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>(want, (uint64_t)ctx->tune.direct_grid_per_cu * ctx->n_cu));
+        const bool lds = ctx->tune.seav_lds && ctx->d.seav_bytes <= 64 * 1024;
+        SPD_HIP(ctx, launch_scan_direct(ctx->c, bd, 1, sp, block, grid, lds, s));
+        ctx->stats.direct_launches++;
+        ctx->stats.pairs_scanned += n;
+        return SPD_OK;
+    }
+    // the most tiles per launch whose region layout (items, spill list, counters) fits the array;
+    // the layout grows with the tile count, so a binary search finds it
+    const uint64_t cap = SPD_NOALLOC_SCRATCH_BYTES;
+    auto layout_of = [&](uint32_t tiles, ChunkTable *ct, uint64_t *iw, uint64_t *cw) {
+        *ct = ChunkTable{};
+        ct->n = 1;
+        ct->hi[0] = tiles;
+        ct->cbase[1] = (tiles + kChunk - 1) / kChunk;
+        RegionArgs ra{};
+        region_layout(ctx, g, *ct, tiles, &ra, iw, cw);
+        return ra.chunk_words < (1ull << 31);
+    };
+    auto fits = [&](uint32_t tiles) {
+        ChunkTable ct;
+        uint64_t iw, cw;
+        if (!layout_of(tiles, &ct, &iw, &cw)) return false;
+        return (cw * 4 + 255) / 256 * 256 + iw * 4 <= cap;
+    };
+    if (!fits(1))
+        return fail(ctx, SPD_E_INVALID, "spd_scan_noalloc: one tile of this sketch geometry needs more scratch than "
+                                        "SPD_NOALLOC_SCRATCH_BYTES");
+    uint32_t lo = 1, hi = (uint32_t)std::min<uint64_t>((n + g.tile_pairs - 1) / g.tile_pairs, 1u << 20);
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (fits(mid)) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint32_t tmax = lo;
+    ChunkTable ct;
+    uint64_t iw, cw;
+    layout_of(tmax, &ct, &iw, &cw);
+    const uint64_t aux_bytes = (cw * 4 + 255) / 256 * 256;
+    // counters first (cleared by the first launch of this call: the array keeps the last call's
+    // contents), then the regions and the spill list
+    bool aux_zero = false;
+    uint32_t parity = 0;
+    const RegionScratch rs{reinterpret_cast<uint32_t *>(ctx->noalloc + aux_bytes), (cap - aux_bytes) / 4,
+                           reinterpret_cast<uint32_t *>(ctx->noalloc), cw, &aux_zero, &parity};
+    const uint64_t max_pairs = (uint64_t)tmax * g.tile_pairs;
+    for (uint64_t off = 0; off < n; off += max_pairs) {
+        const uint64_t cn = std::min(max_pairs, n - off);
+        const uint32_t tiles = (uint32_t)((cn + g.tile_pairs - 1) / g.tile_pairs);
+        layout_of(tiles, &ct, &iw, &cw);
+        const BatchDesc bd{pairs + 2 * off, cn, 0, 0, swap, 0};
+        SlotPtrs sp[kMaxGroup] = {};
+        ApplySlot as[kMaxGroup] = {};
+        bool clean[kMaxGroup] = {};
+        sp[0] = ptrs_of(*sl);
+        as[0] = ApplySlot{sl->ldca, reinterpret_cast<uint32_t *>(sl->seav), 0, tiles, sl->fresh ? 1u : 0u, 0};
+        clean[0] = sl->fresh && sl->seav_zero;
+        spd_status st = region_launch_at(ctx, g, &bd, 1, tiles, ct, sp, as, clean, 1, rs, s);
+        if (st) return st;
+        sl->fresh = false;
+        sl->seav_zero = false;
+        ctx->stats.binned_launches++;
+    }
+    ctx->stats.pairs_scanned += n;
     return SPD_OK;
 }
 
@@ -1102,6 +1242,11 @@ spd_status ctx_create(const spd_params *p, uint32_t n_routers, uint32_t n_slots,
         ctx->est[z] = (uint32_t)std::floor(-k * std::log((double)(z ? z : 1) / k) + 0.5);
 
     DeviceGuard dg(ctx->device);
+    {
+        // the no-alloc scan's scratch on this device; a failed lookup disables only that entry point
+        const hipError_t e = noalloc_lookup(ctx->device, &ctx->noalloc);
+        if (e != hipSuccess) ctx->noalloc_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    }
     ctx->seav_alloc = (ctx->d.seav_bytes + kSeavAlign - 1) / kSeavAlign * kSeavAlign;
     ctx->ldca_bytes = (ctx->d.ldca_words * 4 + 255) / 256 * 256;   // SEAV starts 256-byte aligned
     // sliding: one 16-bit stamp per bit
@@ -1183,6 +1328,24 @@ spd_status spd_scan(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_dev, ui
     if (!ctx) return SPD_E_INVALID;
     spd_batch b{router, 0, pairs_dev, n_pairs};
     return spd_scan_batches(ctx, &b, 1, stream);
+}
+
+spd_status spd_scan_noalloc(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_dev, uint64_t n_pairs, uint32_t flags,
+                            void *stream) {
+    if (!ctx) return SPD_E_INVALID;
+    spd_status st = validate_batch(ctx, spd_batch{router, flags, pairs_dev, n_pairs});
+    if (st) return st;
+    if (ctx->sliding) return fail(ctx, SPD_E_STATE, "spd_scan_noalloc: discrete-window contexts only");
+    if (!ctx->noalloc) return fail(ctx, SPD_E_HIP, "spd_scan_noalloc: " + ctx->noalloc_err);
+    if (n_pairs == 0) return SPD_OK;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    order_stream(ctx, s);
+    const bool prof = ctx->prof_on;   // timing would create events
+    ctx->prof_on = false;
+    st = scan_noalloc(ctx, &ctx->slots[router], pairs_dev, n_pairs, (flags & SPD_BATCH_DST) ? 1u : 0u, s);
+    ctx->prof_on = prof;
+    return st;
 }
 
 spd_status spd_scan_host(spd_ctx *ctx, uint32_t router, const uint32_t *pairs_host, uint64_t n_pairs, uint32_t flags,
