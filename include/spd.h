@@ -62,6 +62,9 @@ typedef struct spd_params {
     uint32_t lr;               /* LDCA rows, 1..SPD_MAX_ROWS */
     uint32_t log2lc;           /* LDCA columns LC = 2^log2lc; 0..24 */
     uint32_t window_slices;    /* 0: discrete window; K > 0: sliding window of K slices (Section 5) */
+    uint32_t sliding_counter;  /* sliding window, the counter that replaces each bit (Section 5.2):
+                                  0 = AT pool, one 8-bit asynchronously maintained time stamp per bit
+                                  (K <= 254); 1 = one exact 16-bit time stamp per bit (K <= 30000) */
     /* Multiply-add-shift hashes h(x) = ((mul * x + add) mod 2^64) >> (64 - bits), mul odd:
      * index 0 = H1 (32 bits), 1 = H2 (3 bits), 2 = H3 (log2k bits), 3 + i = LH_i (log2lc bits). */
     uint64_t hash_mul[3 + SPD_MAX_ROWS];
@@ -215,6 +218,13 @@ spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *st
 spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_host, uint32_t cap,
                             uint32_t *n_out, void *stream);
 
+/* Start a new window for a target without reporting the current one: the re-initialisation of a
+ * watch point's sketch at the start of each window (Sections 3.3, 4.2), e.g. once its sketch has
+ * been merged into the global one.  Discrete mode: the slot is marked empty and its next scan
+ * starts from zero (no device work here).  Sliding mode: every time stamp is cleared, enqueued on
+ * `stream`. */
+spd_status spd_reset(spd_ctx *ctx, int32_t target, void *stream);
+
 /* Sliding mode only: the next scans belong to the next time slice (Section 5.2).  Stamps older
  * than the window simply drop out of the bit view; no state is rewritten. */
 spd_status spd_slide(spd_ctx *ctx, void *stream);
@@ -228,7 +238,9 @@ spd_status spd_import(spd_ctx *ctx, int32_t target, const uint8_t *seav_host, co
 
 /* Sliding mode: copy a target's raw time stamps (1 + last slice that set the bit, 0 = never):
  * seav_ts_host holds seav_bytes * 8 entries (bit b of byte x at 8x + b), ldca_ts_host holds
- * ldca_words * 32 entries (one per LDCA bit). */
+ * ldca_words * 32 entries (one per LDCA bit).  With the AT pool the stamps are rebuilt from the
+ * counters (modulo 2^16); a counter that maintenance has cleared (set more than K slices ago)
+ * reads 0. */
 spd_status spd_export_stamps(spd_ctx *ctx, int32_t target, uint16_t *seav_ts_host, uint16_t *ldca_ts_host);
 
 /* Current slice index (sliding mode; 0 in discrete mode). */
@@ -279,6 +291,8 @@ typedef struct spd_server_config {
                                       pairs wait until this many are queued, its window can end, a close
                                       is requested or drain is called; an idle GPU takes whatever is
                                       queued (0: the larger of 8 Mi and window_pairs / 4) */
+    const spd_tuning *tuning;      /* launch settings of the scans (NULL: the library's defaults); applied
+                                      before the scratch of the largest group is reserved */
 } spd_server_config;
 
 typedef struct spd_window_result {

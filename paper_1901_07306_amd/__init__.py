@@ -30,7 +30,7 @@ u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
 class SpdParams(ctypes.Structure):
     _fields_ = [("theta", u32), ("r", u32), ("sr", u32), ("a", u32), ("explicit_layout", u32),
                 ("isb", u32 * MAX_ROWS), ("ibn", u32 * MAX_ROWS), ("log2k", u32), ("lr", u32),
-                ("log2lc", u32), ("window_slices", u32),
+                ("log2lc", u32), ("window_slices", u32), ("sliding_counter", u32),
                 ("hash_mul", u64 * (3 + MAX_ROWS)), ("hash_add", u64 * (3 + MAX_ROWS))]
 
 
@@ -68,7 +68,8 @@ class SpdProfile(ctypes.Structure):
 
 class SpdServerConfig(ctypes.Structure):
     _fields_ = [("n_routers", u32), ("max_slots", u32), ("window_pairs", u64), ("hbm_budget_bytes", u64),
-                ("max_group_pairs", u64), ("max_group_batches", u32), ("use_graphs", u32), ("min_scan_pairs", u64)]
+                ("max_group_pairs", u64), ("max_group_batches", u32), ("use_graphs", u32), ("min_scan_pairs", u64),
+                ("tuning", ctypes.c_void_p)]
 
 
 class SpdWindowResult(ctypes.Structure):
@@ -89,7 +90,7 @@ class SpdServerStats(ctypes.Structure):
 RECORD = np.dtype([("ip", "<u4"), ("z0", "<u4"), ("est", "<u4"), ("flags", "<u4")])
 
 EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_noalloc", "spd_scan_host", "spd_scan_batches", "spd_merge",
-            "spd_close_window", "spd_slide", "spd_export", "spd_import", "spd_export_stamps",
+            "spd_close_window", "spd_reset", "spd_slide", "spd_export", "spd_import", "spd_export_stamps",
             "spd_current_slice", "spd_get_tuning", "spd_set_tuning", "spd_get_stats", "spd_strerror",
             "spd_last_error", "spd_profile_enable", "spd_profile_select", "spd_get_profile", "spd_server_create", "spd_server_submit",
             "spd_server_next", "spd_server_drain", "spd_server_get_stats", "spd_server_set_tuning",
@@ -149,6 +150,7 @@ def lib(require_torch: bool = True) -> ctypes.CDLL:
         "spd_merge": (i32, [vp, P(u32), u32, vp]),
         "spd_close_window": (i32, [vp, i32, P(SpdSuperpoint), u32, P(u32), vp]),
         "spd_slide": (i32, [vp, vp]),
+        "spd_reset": (i32, [vp, i32, vp]),
         "spd_export": (i32, [vp, i32, vp, vp]),
         "spd_import": (i32, [vp, i32, vp, vp]),
         "spd_export_stamps": (i32, [vp, i32, vp, vp]),
@@ -186,12 +188,17 @@ def _check(status: int, ctx=None):
 
 
 # ------------------------------------------------------------------------------ parameters
+SLIDING_AT, SLIDING_STAMPS = 0, 1   # spd_params.sliding_counter
+
+
 def make_params(theta: int, r: int, sr: int, a: int, log2k: int, lr: int, log2lc: int,
                 hash_mul: Sequence[int], hash_add: Sequence[int], window_slices: int = 0,
-                isb: Optional[Sequence[int]] = None, ibn: Optional[Sequence[int]] = None) -> SpdParams:
+                isb: Optional[Sequence[int]] = None, ibn: Optional[Sequence[int]] = None,
+                sliding_counter: int = SLIDING_AT) -> SpdParams:
     p = SpdParams()
     p.theta, p.r, p.sr, p.a = theta, r, sr, a
     p.log2k, p.lr, p.log2lc, p.window_slices = log2k, lr, log2lc, window_slices
+    p.sliding_counter = sliding_counter
     if isb is not None:
         p.explicit_layout = 1
         for i in range(sr):
@@ -202,10 +209,11 @@ def make_params(theta: int, r: int, sr: int, a: int, log2k: int, lr: int, log2lc
 
 
 def params_from(mp, isb=None, ibn=None) -> SpdParams:
-    """From any object with theta, r, sr, a, log2k, lr, log2lc, window_slices and hashes()."""
+    """From any object with theta, r, sr, a, log2k, lr, log2lc, window_slices, sliding_counter and
+    hashes()."""
     mul, add = mp.hashes()
     return make_params(mp.theta, mp.r, mp.sr, mp.a, mp.log2k, mp.lr, mp.log2lc, mul, add,
-                       getattr(mp, "window_slices", 0), isb, ibn)
+                       getattr(mp, "window_slices", 0), isb, ibn, getattr(mp, "sliding_counter", SLIDING_AT))
 
 
 def spd_derive(p: SpdParams) -> SpdDerived:
@@ -304,6 +312,10 @@ def spd_close_window(ctx: int, target: int, cap: int = 1 << 16, stream=None) -> 
         _check(st, ctx)
         buf = np.frombuffer(out, dtype=RECORD, count=max(1, cap))
         return buf[: n.value].copy()
+
+
+def spd_reset(ctx: int, target: int, stream=None) -> None:
+    _check(lib().spd_reset(ctx, target, _stream_ptr(stream)), ctx)
 
 
 def spd_slide(ctx: int, stream=None) -> None:
@@ -410,6 +422,9 @@ class Detector:
     def close_window(self, target=0, cap=1 << 16, stream=None):
         return spd_close_window(self.ctx, target, cap, stream)
 
+    def reset(self, target=0, stream=None):
+        spd_reset(self.ctx, target, stream)
+
     def slide(self, stream=None):
         spd_slide(self.ctx, stream)
 
@@ -449,10 +464,12 @@ class Server:
 
     def __init__(self, params: SpdParams, n_routers: int, window_pairs: int = 0, hbm_budget_bytes: int = 0,
                  max_slots: int = 0, max_group_pairs: int = 0, max_group_batches: int = 0, use_graphs: bool = True,
-                 min_scan_pairs: int = 0):
+                 min_scan_pairs: int = 0, tuning: Optional[SpdTuning] = None):
         self.params = params
+        self._tuning = tuning
         cfg = SpdServerConfig(n_routers, max_slots, window_pairs, hbm_budget_bytes, max_group_pairs,
-                              max_group_batches, 1 if use_graphs else 0, min_scan_pairs)
+                              max_group_batches, 1 if use_graphs else 0, min_scan_pairs,
+                              ctypes.cast(ctypes.pointer(tuning), ctypes.c_void_p) if tuning is not None else None)
         h = ctypes.c_void_p()
         st = lib().spd_server_create(ctypes.byref(params), ctypes.byref(cfg), ctypes.byref(h))
         if st != SPD_OK:

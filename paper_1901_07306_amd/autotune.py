@@ -14,6 +14,8 @@ from typing import Dict, List, Optional, Tuple
 _CACHE: Dict[tuple, dict] = {}
 
 SCAN_KINDS = ("direct", "bin", "transpose", "apply", "fill", "count", "offsets", "spill")
+TUNED_FIELDS = ("bin_mode", "bucket_bits", "tile_pairs", "bin_block", "apply_block", "apply_unroll",
+                "direct_block", "direct_grid_per_cu", "seav_lds", "direct_max_pairs")
 
 
 def _scan_ms(det, x, reps: int) -> float:
@@ -27,9 +29,13 @@ def _scan_ms(det, x, reps: int) -> float:
 
 
 def candidate_settings(quick: bool = False) -> List[dict]:
+    """Binned-scan settings the tuner times: the layout (bin_mode), the LDS bucket size, the tile,
+    the binning workgroup and the apply kernel's loads in flight per lane."""
     if quick:
         return [dict(bin_mode=2, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024, apply_unroll=16),
                 dict(bin_mode=2, bucket_bits=20, tile_pairs=8192, bin_block=512, apply_block=1024, apply_unroll=16),
+                dict(bin_mode=2, bucket_bits=20, tile_pairs=16384, bin_block=1024, apply_block=1024, apply_unroll=16),
+                dict(bin_mode=2, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024, apply_unroll=32),
                 dict(bin_mode=1, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024, apply_unroll=16),
                 dict(bin_mode=0, bucket_bits=20, tile_pairs=16384, bin_block=1024, apply_block=1024, apply_unroll=16)]
     out = []
@@ -38,17 +44,20 @@ def candidate_settings(quick: bool = False) -> List[dict]:
     return out
 
 
+def _apply(det, settings: dict) -> None:
+    t = det.tuning
+    for k, v in settings.items():
+        setattr(t, k, v)
+    det.tuning = t
+
+
 def tune_binned(det, x, reps: int = 3, quick: bool = False) -> Tuple[dict, List[Tuple[dict, float]]]:
     """Fastest binned-scan setting for batch x on detector det (router 0 is used and reset)."""
     base = det.tuning
     table = []
     for cand in candidate_settings(quick):
-        t = det.tuning
-        for k, v in cand.items():
-            setattr(t, k, v)
-        t.direct_max_pairs = 0
         try:
-            det.tuning = t
+            _apply(det, dict(cand, direct_max_pairs=0))
         except Exception:
             continue
         _scan_ms(det, x, 1)   # warm-up (scratch growth)
@@ -62,12 +71,10 @@ def tune_direct(det, x, reps: int = 3) -> Tuple[dict, List[Tuple[dict, float]]]:
     base = det.tuning
     table = []
     for block, per_cu, lds in itertools.product((256, 512), (4, 8, 16), (0, 1)):
-        t = det.tuning
-        t.direct_max_pairs = 1 << 62
-        t.direct_block, t.direct_grid_per_cu, t.seav_lds = block, per_cu, lds
-        det.tuning = t
+        cand = dict(direct_block=block, direct_grid_per_cu=per_cu, seav_lds=lds)
+        _apply(det, dict(cand, direct_max_pairs=1 << 62))
         _scan_ms(det, x, 1)
-        table.append((dict(direct_block=block, direct_grid_per_cu=per_cu, seav_lds=lds), _scan_ms(det, x, reps)))
+        table.append((cand, _scan_ms(det, x, reps)))
     det.tuning = base
     return min(table, key=lambda e: e[1])[0], table
 
@@ -96,17 +103,36 @@ def crossover(det, x, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22), reps:
 
 
 def autotune(det, x, key: Optional[tuple] = None, quick: bool = False) -> dict:
-    """Tune det for batches like x and apply the result.  Returns the chosen settings."""
+    """Tune det for batches like x and apply the result.  Returns the chosen settings; the timing
+    tables are kept in the cache entry (``last_tables(key)``)."""
     import torch
-    key = key or (torch.cuda.get_device_name(0), tuple(det.params.hash_mul[:3]), det.params.r,
-                  det.params.log2lc, int(x.shape[0]))
+    key = key or cache_key(det, x)
     if key not in _CACHE:
-        b, _ = tune_binned(det, x, quick=quick)
-        d, _ = tune_direct(det, x[: min(x.shape[0], 1 << 20)])
+        b, tb = tune_binned(det, x, quick=quick)
+        d, td = tune_direct(det, x[: min(x.shape[0], 1 << 20)])
         cross = crossover(det, x)
-        _CACHE[key] = dict(b, **d, direct_max_pairs=cross)
+        _CACHE[key] = dict(settings=dict(b, **d, direct_max_pairs=cross), binned=tb, direct=td,
+                           gpu=torch.cuda.get_device_name(0))
+    _apply(det, _CACHE[key]["settings"])
+    return dict(_CACHE[key]["settings"])
+
+
+def cache_key(det, x) -> tuple:
+    import torch
+    p = det.params
+    return (torch.cuda.get_device_name(0), tuple(p.hash_mul[:3]), p.r, p.sr, p.log2k, p.lr, p.log2lc,
+            int(x.shape[0]))
+
+
+def last_tables(key: tuple) -> dict:
+    """The timing tables behind a cached choice: binned candidates and direct-kernel settings (ms)."""
+    e = _CACHE[key]
+    return {"binned": [(c, ms) for c, ms in e["binned"]], "direct": [(c, ms) for c, ms in e["direct"]]}
+
+
+def tuning_of(det, settings: dict):
+    """An spd_tuning structure: det's current tuning with the given settings applied."""
     t = det.tuning
-    for k, v in _CACHE[key].items():
+    for k, v in settings.items():
         setattr(t, k, v)
-    det.tuning = t
-    return dict(_CACHE[key])
+    return t

@@ -41,6 +41,30 @@ def build_library(verbose: bool = False) -> str:
     return LIB
 
 
+CEIL_LIB = os.path.join(PKG, "libspd_ceilings.so")
+CEIL_SOURCES = [os.path.join(PKG, "csrc", "spd_ceilings.hip")]
+
+
+def build_ceilings(verbose: bool = False) -> str:
+    """The microbenchmarks of the hardware ceilings (a library of their own)."""
+    fd, tmp = tempfile.mkstemp(suffix=".so", dir=PKG)
+    os.close(fd)
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I" + os.path.join(ROOT, "include"), "-o", tmp] + CEIL_SOURCES
+    try:
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("libspd_ceilings build failed:\n" + res.stderr)
+        if verbose:
+            print(" ".join(cmd))
+        os.replace(tmp, CEIL_LIB)
+    finally:
+        if os.path.exists(tmp):
+            os.unlink(tmp)
+    return CEIL_LIB
+
+
 def is_stale() -> bool:
     if not os.path.exists(LIB):
         return True

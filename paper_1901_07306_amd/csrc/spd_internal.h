@@ -81,9 +81,28 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t i, uint32_t n) {
 struct SlotPtrs {
     uint8_t *seav;       // padded SEAV (word aligned)
     uint32_t *ldca;
-    uint16_t *seav_ts;   // sliding mode
+    uint16_t *seav_ts;   // sliding mode, 16-bit time stamps
     uint16_t *ldca_ts;
+    uint8_t *seav_at;    // sliding mode, AT pool (one 8-bit counter per bit)
+    uint8_t *ldca_at;
 };
+
+// Sliding window with the AT pool: every bit is an 8-bit counter, 0 = never set, else 1 + (the
+// last slice that set it mod kAtPeriod).  At slice t a counter v != 0 is active (bit 1) iff its
+// age ((t - (v - 1)) mod kAtPeriod) is below K.  Maintenance at every slice start clears the
+// expired counters of one of G = kAtPeriod - K groups of the pool, so each counter is swept at
+// least once every G slices and its true age stays below K + G = kAtPeriod while it is nonzero:
+// the age read modulo kAtPeriod is then the true age.
+constexpr uint32_t kAtPeriod = 255;
+__host__ __device__ __forceinline__ uint32_t at_code(uint32_t slice) { return slice % kAtPeriod + 1u; }
+__device__ __forceinline__ uint32_t at_active(uint32_t v, uint32_t tm, uint32_t K) {
+    int d = (int)tm - (int)v + 1;   // tm = t mod kAtPeriod
+    d += d < 0 ? (int)kAtPeriod : 0;
+    return (v != 0u && (uint32_t)d < K) ? 1u : 0u;
+}
+
+// What the end-of-window kernel reads: bits, 16-bit time stamps, or AT counters.
+enum CloseMode : int { kCloseBits = 0, kCloseStamps = 1, kCloseAt = 2 };
 
 struct BatchDesc {
     const uint32_t *pairs;
@@ -118,8 +137,20 @@ struct BinGeometry {
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n_words, uint32_t value, hipStream_t s);
 hipError_t launch_scan_direct(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
                               uint32_t block, uint32_t grid, bool seav_lds, hipStream_t s);
+// Sliding scan: every bit the discrete scan would set receives `value` (a 16-bit stamp, or an AT
+// code when at is set).
 hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
-                             uint16_t stamp, uint32_t block, uint32_t grid, hipStream_t s);
+                             uint32_t value, bool at, uint32_t block, uint32_t grid, hipStream_t s);
+// AT pool maintenance: clears the counters of bytes [lo, hi) of each of n pools (hi <= pool bytes,
+// lo and hi multiples of 16) that are expired at the slice whose code is tm + 1.
+hipError_t launch_at_sweep(uint8_t *const *pools, uint32_t n, uint64_t lo, uint64_t hi, uint32_t tm, uint32_t K,
+                           hipStream_t s);
+// dst = per counter the most recent of the n_src pools (the AT version of the OR merge).
+hipError_t launch_at_merge(uint8_t *dst, const uint8_t *const *src, uint32_t n_src, uint64_t n_bytes, uint32_t tm,
+                           hipStream_t s);
+// Bit view of AT counters: bit j of word w is 1 iff counter 32 w + j is active.
+hipError_t launch_bit_view_at(const uint8_t *at, uint64_t n_bits, uint32_t tm, uint32_t K, uint32_t *out_words,
+                              hipStream_t s);
 hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
                       uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s);
 hipError_t launch_transpose(const uint32_t *meta, uint32_t *metaT, uint32_t rows, uint32_t cols, hipStream_t s);
@@ -213,7 +244,11 @@ struct CloseArgs {
     const uint32_t *ldca;
     const uint16_t *seav_ts;
     const uint16_t *ldca_ts;
-    uint32_t thr;        // sliding: stamp threshold of the bit view
+    const uint8_t *seav_at;
+    const uint8_t *ldca_at;
+    uint32_t thr;        // sliding, 16-bit stamps: stamp threshold of the bit view
+    uint32_t at_tm;      // sliding, AT pool: current slice mod kAtPeriod
+    uint32_t at_k;       // sliding, AT pool: window length K
     uint32_t *rec;       // (ip, z0) pairs
     uint32_t *counters;  // [0] reported, [1] candidates
     uint32_t rec_cap;
@@ -222,9 +257,8 @@ struct CloseArgs {
     uint32_t qcap;
     uint32_t stage_words;  // LDS words per wavefront holding one SEA (its bit view when sliding)
 };
-hipError_t launch_close(const Consts &c, const CloseArgs &a, bool sliding, uint32_t block, uint32_t grid,
-                        hipStream_t s);
+hipError_t launch_close(const Consts &c, const CloseArgs &a, int mode, uint32_t block, uint32_t grid, hipStream_t s);
 // Workgroups of the end-of-window kernel that one compute unit holds at once (registers and LDS).
-uint32_t close_blocks_per_cu(bool sliding, uint32_t block, uint32_t lds_bytes);
+uint32_t close_blocks_per_cu(int mode, uint32_t block, uint32_t lds_bytes);
 
 }  // namespace spd

@@ -193,40 +193,169 @@ hipError_t launch_scan_direct(const Consts &c, const BatchDesc *batches, uint32_
 }
 
 // ------------------------------------------------------------------------------ sliding scan
-// Every bit the discrete scan would set receives the slice's stamp.  All writers of one slice
-// store the same value, and slices are ordered by the stream, so plain stores suffice.
-__global__ __launch_bounds__(1024) void k_scan_stamp(Consts c, BatchTable bt, SlotTable st, uint32_t stamp) {
+// Every bit the discrete scan would set receives the slice's value: a 16-bit stamp, or an 8-bit
+// AT code.  All writers of one slice store the same value, and slices are ordered by the stream,
+// so plain stores suffice.
+template <typename T>
+__device__ __forceinline__ T *ldca_counters(const SlotPtrs &S);
+template <>
+__device__ __forceinline__ uint16_t *ldca_counters<uint16_t>(const SlotPtrs &S) { return S.ldca_ts; }
+template <>
+__device__ __forceinline__ uint8_t *ldca_counters<uint8_t>(const SlotPtrs &S) { return S.ldca_at; }
+template <typename T>
+__device__ __forceinline__ T *seav_counters(const SlotPtrs &S);
+template <>
+__device__ __forceinline__ uint16_t *seav_counters<uint16_t>(const SlotPtrs &S) { return S.seav_ts; }
+template <>
+__device__ __forceinline__ uint8_t *seav_counters<uint8_t>(const SlotPtrs &S) { return S.seav_at; }
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_stamp(Consts c, BatchTable bt, SlotTable st, uint32_t value) {
     const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint16_t v = (uint16_t)stamp;
+    const T v = (T)value;
     for (uint32_t bi = 0; bi < bt.n; ++bi) {
         const BatchDesc B = bt.b[bi];
         const SlotPtrs S = st.s[B.slot];
+        T *ldca = ldca_counters<T>(S), *seav = seav_counters<T>(S);
         const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
         for (uint64_t i = gtid; i < B.n; i += stride) {
             const u32x2 pr = load_pair(pairs, i, B.swap);
             const uint32_t hip = pr.x, oip = pr.y;
             const uint32_t q = ldc_bit(oip, c);
-            for (uint32_t r = 0; r < c.lr; ++r) S.ldca_ts[ldca_bit(r, ldc_col(hip, r, c), q, c)] = v;
+            for (uint32_t r = 0; r < c.lr; ++r) ldca[ldca_bit(r, ldc_col(hip, r, c), q, c)] = v;
             if (sampled(oip, c)) {
                 const uint32_t b = se_bit(oip, c);
-                for (uint32_t r = 0; r < c.sr; ++r) {
-                    S.seav_ts[(uint64_t)seav_byte(hip, r, c) * 8u + b] = v;
-                }
+                for (uint32_t r = 0; r < c.sr; ++r) seav[(uint64_t)seav_byte(hip, r, c) * 8u + b] = v;
             }
         }
     }
 }
 
 hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
-                             uint16_t stamp, uint32_t block, uint32_t grid, hipStream_t s) {
+                             uint32_t value, bool at, uint32_t block, uint32_t grid, hipStream_t s) {
     BatchTable bt{};
     SlotTable st{};
     if (n_batches > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
     for (uint32_t i = 0; i < n_batches; ++i) bt.b[i] = batches[i];
     bt.n = n_batches;
     for (int i = 0; i < kMaxGroup; ++i) st.s[i] = slots[i];
-    hipLaunchKernelGGL(k_scan_stamp, dim3(grid), dim3(block), 0, s, c, bt, st, (uint32_t)stamp);
+    if (at) hipLaunchKernelGGL(k_scan_stamp<uint8_t>, dim3(grid), dim3(block), 0, s, c, bt, st, value);
+    else hipLaunchKernelGGL(k_scan_stamp<uint16_t>, dim3(grid), dim3(block), 0, s, c, bt, st, value);
+    return hipGetLastError();
+}
+
+// AT pool maintenance and views.  A pool is handled 16 counters (one 16-byte vector) per lane.
+struct PoolTable {
+    uint8_t *p[kMaxGroup];
+};
+struct CPoolTable {
+    const uint8_t *p[kMaxGroup];
+};
+
+// Byte k of a 16-byte vector.
+__device__ __forceinline__ uint32_t byte_of(const u32x4 &v, uint32_t k) { return (v[k >> 2] >> (8 * (k & 3))) & 0xFFu; }
+
+__global__ __launch_bounds__(256) void k_at_sweep(PoolTable pt, uint32_t n, uint64_t lo16, uint64_t hi16, uint32_t tm,
+                                                  uint32_t K) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint32_t k = 0; k < n; ++k) {
+        u32x4 *p = reinterpret_cast<u32x4 *>(pt.p[k]);
+        for (uint64_t i = lo16 + blockIdx.x * (uint64_t)256 + threadIdx.x; i < hi16; i += stride) {
+            const u32x4 v = p[i];
+            u32x4 o = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (uint32_t b = 0; b < 16; ++b) {
+                const uint32_t x = byte_of(v, b);
+                if (at_active(x, tm, K)) o[b >> 2] |= x << (8 * (b & 3));
+            }
+            if (o.x != v.x || o.y != v.y || o.z != v.z || o.w != v.w) p[i] = o;
+        }
+    }
+}
+
+hipError_t launch_at_sweep(uint8_t *const *pools, uint32_t n, uint64_t lo, uint64_t hi, uint32_t tm, uint32_t K,
+                           hipStream_t s) {
+    if (lo % 16 || hi % 16 || hi < lo) return hipErrorInvalidValue;
+    for (uint32_t k0 = 0; k0 < n; k0 += kMaxGroup) {
+        PoolTable pt{};
+        const uint32_t m = n - k0 < (uint32_t)kMaxGroup ? n - k0 : (uint32_t)kMaxGroup;
+        for (uint32_t k = 0; k < m; ++k) pt.p[k] = pools[k0 + k];
+        const uint64_t vec = (hi - lo) / 16;
+        if (vec == 0) return hipSuccess;
+        const uint32_t grid = (uint32_t)((vec + 255) / 256 < 2048 ? (vec + 255) / 256 : 2048);
+        hipLaunchKernelGGL(k_at_sweep, dim3(grid), dim3(256), 0, s, pt, m, lo / 16, hi / 16, tm, K);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Per counter, the most recent of the sources: the smallest age among nonzero counters.  Every
+// source is maintained, so every nonzero age read modulo kAtPeriod is the true age.
+__global__ __launch_bounds__(256) void k_at_merge(uint8_t *__restrict__ dst, CPoolTable src, uint32_t n_src,
+                                                  uint64_t n16, uint32_t tm) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = blockIdx.x * (uint64_t)256 + threadIdx.x; i < n16; i += stride) {
+        uint32_t best[16], age[16];
+#pragma unroll
+        for (uint32_t b = 0; b < 16; ++b) {
+            best[b] = 0u;
+            age[b] = kAtPeriod;
+        }
+        for (uint32_t k = 0; k < n_src; ++k) {
+            const u32x4 v = reinterpret_cast<const u32x4 *>(src.p[k])[i];
+#pragma unroll
+            for (uint32_t b = 0; b < 16; ++b) {
+                const uint32_t x = byte_of(v, b);
+                int d = (int)tm - (int)x + 1;
+                d += d < 0 ? (int)kAtPeriod : 0;
+                if (x != 0u && (uint32_t)d < age[b]) {
+                    age[b] = (uint32_t)d;
+                    best[b] = x;
+                }
+            }
+        }
+        u32x4 o = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (uint32_t b = 0; b < 16; ++b) o[b >> 2] |= best[b] << (8 * (b & 3));
+        reinterpret_cast<u32x4 *>(dst)[i] = o;
+    }
+}
+
+hipError_t launch_at_merge(uint8_t *dst, const uint8_t *const *src, uint32_t n_src, uint64_t n_bytes, uint32_t tm,
+                           hipStream_t s) {
+    if (n_src == 0 || n_src > (uint32_t)kMaxGroup || n_bytes % 16) return hipErrorInvalidValue;
+    CPoolTable t{};
+    for (uint32_t k = 0; k < n_src; ++k) t.p[k] = src[k];
+    const uint64_t n16 = n_bytes / 16;
+    const uint32_t grid = (uint32_t)((n16 + 255) / 256 < 8192 ? (n16 + 255) / 256 : 8192);
+    hipLaunchKernelGGL(k_at_merge, dim3(grid ? grid : 1), dim3(256), 0, s, dst, t, n_src, n16, tm);
+    return hipGetLastError();
+}
+
+// Bit view of AT counters: 32 counters (two 16-byte vectors) per output word.
+__global__ __launch_bounds__(256) void k_bit_view_at(const uint8_t *__restrict__ at, uint64_t n_words, uint32_t tm,
+                                                     uint32_t K, uint32_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t w = blockIdx.x * (uint64_t)256 + threadIdx.x; w < n_words; w += stride) {
+        const u32x4 a = reinterpret_cast<const u32x4 *>(at)[2 * w], b = reinterpret_cast<const u32x4 *>(at)[2 * w + 1];
+        uint32_t v = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < 16; ++j) {
+            v |= at_active(byte_of(a, j), tm, K) << j;
+            v |= at_active(byte_of(b, j), tm, K) << (16 + j);
+        }
+        out[w] = v;
+    }
+}
+
+hipError_t launch_bit_view_at(const uint8_t *at, uint64_t n_bits, uint32_t tm, uint32_t K, uint32_t *out_words,
+                              hipStream_t s) {
+    if (n_bits % 32) return hipErrorInvalidValue;
+    const uint64_t words = n_bits / 32;
+    const uint32_t grid = (uint32_t)((words + 255) / 256 < 8192 ? (words + 255) / 256 : 8192);
+    hipLaunchKernelGGL(k_bit_view_at, dim3(grid ? grid : 1), dim3(256), 0, s, at, words, tm, K, out_words);
     return hipGetLastError();
 }
 
@@ -1476,22 +1605,41 @@ hipError_t launch_bit_view(const uint16_t *ts, uint64_t n_bits, uint16_t thr, ui
 }
 
 // ------------------------------------------------------------------------------ end of window
-template <bool SLIDING>
+// Bit view of the four AT counters packed in one 32-bit word (counter j in byte j).
+__device__ __forceinline__ uint32_t at_bits4(uint32_t w, const CloseArgs &a) {
+    return at_active(w & 0xFFu, a.at_tm, a.at_k) | at_active((w >> 8) & 0xFFu, a.at_tm, a.at_k) << 1 |
+           at_active((w >> 16) & 0xFFu, a.at_tm, a.at_k) << 2 | at_active(w >> 24, a.at_tm, a.at_k) << 3;
+}
+
+// One SEAV byte as bits: the byte itself, or the bit view of its 8 counters.
+template <int MODE>
 __device__ __forceinline__ uint32_t load_se(const CloseArgs &a, uint64_t byte) {
-    if (!SLIDING) return a.seav[byte];
-    const uint16_t *t = a.seav_ts + byte * 8;
+    if (MODE == kCloseBits) return a.seav[byte];
     uint32_t v = 0;
-    for (uint32_t j = 0; j < 8; ++j) v |= (t[j] >= a.thr ? 1u : 0u) << j;
+    if (MODE == kCloseStamps) {
+        const uint16_t *t = a.seav_ts + byte * 8;
+        for (uint32_t j = 0; j < 8; ++j) v |= (t[j] >= a.thr ? 1u : 0u) << j;
+    } else {
+        const uint64_t t = *reinterpret_cast<const uint64_t *>(a.seav_at + byte * 8);
+        v = at_bits4((uint32_t)t, a) | at_bits4((uint32_t)(t >> 32), a) << 4;
+    }
     return v;
 }
 
-// word < 2^27: a sketch has fewer than 2^32 bits
-template <bool SLIDING>
+// One LDCA word as bits (word < 2^27: a sketch has fewer than 2^32 bits).
+template <int MODE>
 __device__ __forceinline__ uint32_t load_ldc_word(const CloseArgs &a, uint32_t word) {
-    if (!SLIDING) return a.ldca[word];
-    const uint16_t *t = a.ldca_ts + word * 32;
+    if (MODE == kCloseBits) return a.ldca[word];
     uint32_t v = 0;
-    for (uint32_t j = 0; j < 32; ++j) v |= (t[j] >= a.thr ? 1u : 0u) << j;
+    if (MODE == kCloseStamps) {
+        const uint16_t *t = a.ldca_ts + (uint64_t)word * 32;
+        for (uint32_t j = 0; j < 32; ++j) v |= (t[j] >= a.thr ? 1u : 0u) << j;
+    } else {
+        const u32x4 *t = reinterpret_cast<const u32x4 *>(a.ldca_at + (uint64_t)word * 32);
+        const u32x4 x = t[0], y = t[1];
+        v = at_bits4(x.x, a) | at_bits4(x.y, a) << 4 | at_bits4(x.z, a) << 8 | at_bits4(x.w, a) << 12 |
+            at_bits4(y.x, a) << 16 | at_bits4(y.y, a) << 20 | at_bits4(y.z, a) << 24 | at_bits4(y.w, a) << 28;
+    }
     return v;
 }
 
@@ -1509,9 +1657,9 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // ULDC of every queued candidate: AND of its LR LDCs, z0 = k - popcount; report if z0 <= z_theta.
 // Four candidates at a time, 16 lanes each; a lane reads 8 words of each of two LDCs before it
 // waits, so one round trip to memory serves four candidates (k = 4096, LR = 2).
-template <bool SLIDING>
+template <int MODE>
 __device__ void filter_queue(const CloseArgs &a, const Consts &c, const uint32_t *queue, uint32_t qn, uint32_t lane) {
-    constexpr uint32_t G = 16, W = SLIDING ? 2 : 8, RB = SLIDING ? 1 : 2;
+    constexpr uint32_t G = 16, W = MODE == kCloseBits ? 8 : MODE == kCloseStamps ? 2 : 1, RB = MODE != kCloseBits ? 1 : 2;
     const uint32_t words = 1u << (c.log2k - 5);
     const uint32_t grp = lane / G, sub = lane % G;
     for (uint32_t e0 = 0; e0 < qn; e0 += 64 / G) {
@@ -1531,7 +1679,7 @@ __device__ void filter_queue(const CloseArgs &a, const Consts &c, const uint32_t
 #pragma unroll
                     for (uint32_t k = 0; k < W; ++k) {
                         const uint32_t w = w0 + k * G + sub;
-                        v[rr][k] = load_ldc_word<SLIDING>(a, base + (w < words ? w : words - 1));
+                        v[rr][k] = load_ldc_word<MODE>(a, base + (w < words ? w : words - 1));
                     }
                 }
 #pragma unroll
@@ -1555,7 +1703,7 @@ __device__ void filter_queue(const CloseArgs &a, const Consts &c, const uint32_t
     }
 }
 
-template <bool SLIDING, int BLOCK>
+template <int MODE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_close(Consts c, CloseArgs a) {
     extern __shared__ uint32_t lds[];
     constexpr uint32_t NW = BLOCK / 64;
@@ -1572,22 +1720,28 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     for (uint32_t rp = blockIdx.x * NW + wid; rp < a.n_rp; rp += gridDim.x * NW) {
         const uint64_t sea = (uint64_t)rp * c.sea_bytes;
         // stage the whole SEA in LDS (when it fits), eight loads in flight per lane
-        auto se_at = [&](uint32_t byte) -> uint32_t { return staged ? sea8[byte] : load_se<SLIDING>(a, sea + byte); };
+        auto se_at = [&](uint32_t byte) -> uint32_t { return staged ? sea8[byte] : load_se<MODE>(a, sea + byte); };
         for (uint32_t b0 = 0; staged && b0 < c.sea_bytes; b0 += 64 * 8) {
             uint32_t v[8];
 #pragma unroll
             for (uint32_t k = 0; k < 8; ++k) {
                 const uint32_t b = b0 + k * 64 + lane;
-                v[k] = load_se<SLIDING>(a, sea + (b < c.sea_bytes ? b : c.sea_bytes - 1));
+                v[k] = load_se<MODE>(a, sea + (b < c.sea_bytes ? b : c.sea_bytes - 1));
             }
 #pragma unroll
             for (uint32_t k = 0; k < 8; ++k)
                 if (b0 + k * 64 + lane < c.sea_bytes) sea8[b0 + k * 64 + lane] = (uint8_t)v[k];
         }
         wave_lds_sync();
+        // Row loops run over kMaxRows with constant indices (guarded by the row count), so the
+        // per-row arrays stay in registers and the row constants are read from the kernel
+        // arguments directly.
         uint32_t cnt[kMaxRows];
         bool empty = false;
-        for (uint32_t i = 0; i < c.sr; ++i) {
+#pragma unroll
+        for (uint32_t i = 0; i < (uint32_t)kMaxRows; ++i) {
+            cnt[i] = 1;
+            if (i >= c.sr || empty) continue;
             const uint32_t cells = 1u << c.ibn[i];
             uint32_t n_hot = 0;
             for (uint32_t c0 = 0; c0 < cells; c0 += 64) {
@@ -1599,26 +1753,27 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                 n_hot += (uint32_t)__popcll(bal);
             }
             cnt[i] = n_hot;
-            if (n_hot == 0) {
-                empty = true;
-                break;
-            }
+            empty = n_hot == 0;
         }
         if (empty) continue;
         wave_lds_sync();
         uint64_t total = 1;
-        for (uint32_t i = 0; i < c.sr; ++i) total *= cnt[i];
+#pragma unroll
+        for (uint32_t i = 0; i < (uint32_t)kMaxRows; ++i) total *= cnt[i];
         uint32_t qn = 0;
         if (total <= lmask + 1ull) {
             // the product CIS of the hot lists (Section 3.2), one tuple per lane.  A lane's tuple
             // index is kept as mixed-radix digits (row 0 least significant) and advanced by 64 each
-            // round with a precomputed digit step, without division.
-            uint32_t dg[kMaxRows];
+            // round by adding the digits of 64, computed once per SEA: no division in the loop.
+            uint32_t dg[kMaxRows], st[kMaxRows];
             {
-                uint32_t rem = lane;
-                for (uint32_t i = 0; i < c.sr; ++i) {
+                uint32_t rem = lane, inc = 64;
+#pragma unroll
+                for (uint32_t i = 0; i < (uint32_t)kMaxRows; ++i) {
                     dg[i] = rem % cnt[i];
                     rem /= cnt[i];
+                    st[i] = inc % cnt[i];
+                    inc /= cnt[i];
                 }
             }
             for (uint64_t u0 = 0; u0 < total; u0 += 64) {
@@ -1628,7 +1783,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                 if (u < total) {
                     uint32_t lp = 0, seu = 0xFFu;
                     uint32_t ci[kMaxRows];
-                    for (uint32_t i = 0; i < c.sr; ++i) {
+#pragma unroll
+                    for (uint32_t i = 0; i < (uint32_t)kMaxRows; ++i) {
+                        ci[i] = 0;
+                        if (i >= c.sr) continue;
                         uint32_t e = lists[i * a.list_stride + dg[i]];
                         ci[i] = e >> 8;
                         seu &= e & 0xFFu;
@@ -1636,18 +1794,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                     }
                     // Eq. 3: the rebuilt LP must give back every row index (overlap bits agree)
                     bool ok = __popc(seu) >= kSeHot;
-                    for (uint32_t i = 0; i < c.sr; ++i) ok = ok && (row_index(lp, c.isb[i], c.ibn[i], c.L) == ci[i]);
+#pragma unroll
+                    for (uint32_t i = 0; i < (uint32_t)kMaxRows; ++i)
+                        if (i < c.sr) ok = ok && (row_index(lp, c.isb[i], c.ibn[i], c.L) == ci[i]);
                     if (ok) {
                         cand = true;
                         h = (uint32_t)(((uint64_t)lp << c.r) | rp);
                     }
                 }
-                // advance the digits by 64, whose digits are (64 mod cnt[0], (64 / cnt[0]) mod cnt[1], ...);
-                // each sum stays below twice its radix, so it wraps at most once
-                uint32_t carry = 0, inc = 64;
-                for (uint32_t i = 0; i < c.sr; ++i) {
-                    const uint32_t d = dg[i] + inc % cnt[i] + carry;
-                    inc /= cnt[i];
+                // advance the digits by 64; each sum stays below twice its radix, so it wraps at
+                // most once (rows past the row count have radix 1 and stay 0)
+                uint32_t carry = 0;
+#pragma unroll
+                for (uint32_t i = 0; i < (uint32_t)kMaxRows; ++i) {
+                    const uint32_t d = dg[i] + st[i] + carry;
                     carry = d >= cnt[i] ? 1u : 0u;
                     dg[i] = carry ? d - cnt[i] : d;
                 }
@@ -1656,7 +1816,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                 qn += (uint32_t)__popcll(bal);
                 if (qn + 64 > a.qcap) {
                     wave_lds_sync();
-                    filter_queue<SLIDING>(a, c, queue, qn, lane);
+                    filter_queue<MODE>(a, c, queue, qn, lane);
                     n_cand += qn;
                     qn = 0;
                 }
@@ -1668,8 +1828,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                 bool cand = false;
                 if (l <= lmask) {
                     uint32_t seu = 0xFFu;
-                    for (uint32_t i = 0; i < c.sr; ++i)
-                        seu &= se_at(c.row_off[i] + row_index((uint32_t)l, c.isb[i], c.ibn[i], c.L));
+#pragma unroll
+                    for (uint32_t i = 0; i < (uint32_t)kMaxRows; ++i)
+                        if (i < c.sr) seu &= se_at(c.row_off[i] + row_index((uint32_t)l, c.isb[i], c.ibn[i], c.L));
                     cand = __popc(seu) >= kSeHot;
                 }
                 const uint64_t bal = __ballot(cand);
@@ -1677,14 +1838,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                 qn += (uint32_t)__popcll(bal);
                 if (qn + 64 > a.qcap) {
                     wave_lds_sync();
-                    filter_queue<SLIDING>(a, c, queue, qn, lane);
+                    filter_queue<MODE>(a, c, queue, qn, lane);
                     n_cand += qn;
                     qn = 0;
                 }
             }
         }
         wave_lds_sync();
-        filter_queue<SLIDING>(a, c, queue, qn, lane);
+        filter_queue<MODE>(a, c, queue, qn, lane);
         n_cand += qn;
         wave_lds_sync();
     }
@@ -1699,33 +1860,38 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     }
 }
 
-uint32_t close_blocks_per_cu(bool sliding, uint32_t block, uint32_t lds_bytes) {
+template <int MODE>
+static uint32_t close_occupancy(uint32_t block, uint32_t lds_bytes) {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
-    if (block == 256) e = sliding ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<true, 256>, 256, lds_bytes)
-                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<false, 256>, 256, lds_bytes);
-    else if (block == 128) e = sliding ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<true, 128>, 128, lds_bytes)
-                                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<false, 128>, 128, lds_bytes);
-    else if (block == 64) e = sliding ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<true, 64>, 64, lds_bytes)
-                                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<false, 64>, 64, lds_bytes);
+    if (block == 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<MODE, 256>, 256, lds_bytes);
+    else if (block == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<MODE, 128>, 128, lds_bytes);
+    else if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_close<MODE, 64>, 64, lds_bytes);
     return (e == hipSuccess && n > 0) ? (uint32_t)n : 1u;
 }
 
-hipError_t launch_close(const Consts &c, const CloseArgs &a, bool sliding, uint32_t block, uint32_t grid, hipStream_t s) {
-    uint32_t lds = (block / 64) * (c.sr * a.list_stride + a.qcap + a.stage_words) * 4u;
-    if (block == 256) {
-        if (sliding) hipLaunchKernelGGL((k_close<true, 256>), dim3(grid), dim3(256), lds, s, c, a);
-        else hipLaunchKernelGGL((k_close<false, 256>), dim3(grid), dim3(256), lds, s, c, a);
-    } else if (block == 128) {
-        if (sliding) hipLaunchKernelGGL((k_close<true, 128>), dim3(grid), dim3(128), lds, s, c, a);
-        else hipLaunchKernelGGL((k_close<false, 128>), dim3(grid), dim3(128), lds, s, c, a);
-    } else if (block == 64) {
-        if (sliding) hipLaunchKernelGGL((k_close<true, 64>), dim3(grid), dim3(64), lds, s, c, a);
-        else hipLaunchKernelGGL((k_close<false, 64>), dim3(grid), dim3(64), lds, s, c, a);
-    } else {
-        return hipErrorInvalidConfiguration;
-    }
+uint32_t close_blocks_per_cu(int mode, uint32_t block, uint32_t lds_bytes) {
+    if (mode == kCloseStamps) return close_occupancy<kCloseStamps>(block, lds_bytes);
+    if (mode == kCloseAt) return close_occupancy<kCloseAt>(block, lds_bytes);
+    return close_occupancy<kCloseBits>(block, lds_bytes);
+}
+
+template <int MODE>
+static hipError_t launch_close_mode(const Consts &c, const CloseArgs &a, uint32_t block, uint32_t grid, uint32_t lds,
+                                    hipStream_t s) {
+    if (block == 256) hipLaunchKernelGGL((k_close<MODE, 256>), dim3(grid), dim3(256), lds, s, c, a);
+    else if (block == 128) hipLaunchKernelGGL((k_close<MODE, 128>), dim3(grid), dim3(128), lds, s, c, a);
+    else if (block == 64) hipLaunchKernelGGL((k_close<MODE, 64>), dim3(grid), dim3(64), lds, s, c, a);
+    else return hipErrorInvalidConfiguration;
     return hipGetLastError();
+}
+
+hipError_t launch_close(const Consts &c, const CloseArgs &a, int mode, uint32_t block, uint32_t grid, hipStream_t s) {
+    const uint32_t lds = (block / 64) * (c.sr * a.list_stride + a.qcap + a.stage_words) * 4u;
+    if (mode == kCloseStamps) return launch_close_mode<kCloseStamps>(c, a, block, grid, lds, s);
+    if (mode == kCloseAt) return launch_close_mode<kCloseAt>(c, a, block, grid, lds, s);
+    if (mode == kCloseBits) return launch_close_mode<kCloseBits>(c, a, block, grid, lds, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace spd

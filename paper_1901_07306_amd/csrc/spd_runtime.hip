@@ -24,6 +24,8 @@ struct Slot {
     uint8_t *seav = nullptr;
     uint16_t *ldca_ts = nullptr;
     uint16_t *seav_ts = nullptr;
+    uint8_t *ldca_at = nullptr;  // AT pool: one 8-bit counter per bit
+    uint8_t *seav_at = nullptr;
     bool fresh = true;           // logically all zero; device memory not yet cleared
     bool seav_zero = false;      // fresh, and its SEAV already zeroed (after the close that reset it)
 };
@@ -68,6 +70,8 @@ struct spd_ctx {
     uint64_t budget = 0;
     uint64_t held = 0;
     bool sliding = false;
+    bool at = false;             // sliding window kept in the AT pool (else 16-bit stamps)
+    uint32_t at_groups = 0;      // AT pool: groups swept round robin, one per slice
     uint32_t K = 0;
     uint32_t slice = 0;
     uint64_t seav_alloc = 0;     // padded SEAV bytes per slot
@@ -205,6 +209,9 @@ spd_status derive(const spd_params *p, spd_derived *d, std::string *why) {
     if (p->log2k < 5 || p->log2k > 16) return bad("log2k must be in [5, 16]");
     if (p->log2lc > 24) return bad("log2lc must be <= 24");
     if (p->window_slices > 30000) return bad("window_slices must be <= 30000");
+    if (p->sliding_counter > 1) return bad("sliding_counter must be 0 (AT pool) or 1 (16-bit stamps)");
+    if (p->window_slices && p->sliding_counter == 0 && p->window_slices > kAtPeriod - 1)
+        return bad("the AT pool needs window_slices <= 254 (use sliding_counter = 1)");
     const uint32_t L = 32 - p->r;
     std::memset(d, 0, sizeof(*d));
     if (p->explicit_layout) {
@@ -358,6 +365,8 @@ SlotPtrs ptrs_of(const Slot &s) {
     p.ldca = s.ldca;
     p.seav_ts = s.seav_ts;
     p.ldca_ts = s.ldca_ts;
+    p.seav_at = s.seav_at;
+    p.ldca_at = s.ldca_at;
     return p;
 }
 
@@ -727,7 +736,8 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                 1, std::min<uint64_t>(want, (uint64_t)ctx->tune.direct_grid_per_cu * ctx->n_cu));
             if (stamp) {
                 ProfScope ps(ctx, SPD_K_STAMP, s);
-                SPD_HIP(ctx, launch_scan_stamp(ctx->c, bd, nbd, sp, (uint16_t)(ctx->slice + 1), block, grid, s));
+                const uint32_t value = ctx->at ? at_code(ctx->slice) : (ctx->slice + 1) & 0xFFFFu;
+                SPD_HIP(ctx, launch_scan_stamp(ctx->c, bd, nbd, sp, value, ctx->at, block, grid, s));
             } else {
                 const bool lds = ctx->tune.seav_lds && nsl == 1 && ctx->d.seav_bytes <= 64 * 1024;
                 ProfScope ps(ctx, SPD_K_DIRECT, s);
@@ -1023,6 +1033,8 @@ void close_buf_free(spd_ctx *ctx, CloseBuf &cb) {
     cb.rec_cap = cb.h_rec_cap = 0;
 }
 
+int close_mode(const spd_ctx *ctx) { return ctx->at ? kCloseAt : ctx->sliding ? kCloseStamps : kCloseBits; }
+
 // Arguments and launch shape of the end-of-window kernel for one slot.
 spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArgs *a, uint32_t *block, uint32_t *grid) {
     *a = CloseArgs{};
@@ -1030,6 +1042,10 @@ spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArg
     a->ldca = sl.ldca;
     a->seav_ts = sl.seav_ts;
     a->ldca_ts = sl.ldca_ts;
+    a->seav_at = sl.seav_at;
+    a->ldca_at = sl.ldca_at;
+    a->at_tm = ctx->slice % kAtPeriod;
+    a->at_k = ctx->K;
     if (ctx->sliding) {
         const int64_t lo = (int64_t)ctx->slice - (int64_t)ctx->K + 2;
         a->thr = lo < 1 ? 1u : (uint32_t)lo;
@@ -1056,7 +1072,8 @@ spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArg
     const uint64_t want = ((uint64_t)a->n_rp + waves - 1) / waves;
     *block = b;
     // one round of resident workgroups; each wavefront then takes SEAs round robin
-    if (!ctx->close_per_cu[b / 128]) ctx->close_per_cu[b / 128] = close_blocks_per_cu(ctx->sliding, b, (uint32_t)((b / 64) * per_wave * 4));
+    if (!ctx->close_per_cu[b / 128])
+        ctx->close_per_cu[b / 128] = close_blocks_per_cu(close_mode(ctx), b, (uint32_t)((b / 64) * per_wave * 4));
     const uint64_t resident = (uint64_t)ctx->n_cu * ctx->close_per_cu[b / 128];
     *grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, resident));
     return SPD_OK;
@@ -1072,7 +1089,7 @@ spd_status close_launch_ops(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStrea
     SPD_HIP(ctx, launch_fill_u32(cb.counters, 4, 0u, s));
     {
         ProfScope ps(ctx, SPD_K_CLOSE, s);
-        SPD_HIP(ctx, launch_close(ctx->c, a, ctx->sliding, block, grid, s));
+        SPD_HIP(ctx, launch_close(ctx->c, a, close_mode(ctx), block, grid, s));
     }
     SPD_HIP(ctx, hipMemcpyAsync(cb.h_counters, cb.counters, 16 + (uint64_t)std::min(cb.rec_cap, kRecChunk) * 8,
                                 hipMemcpyDeviceToHost, s));
@@ -1169,7 +1186,12 @@ spd_status slot_alloc(spd_ctx *ctx, Slot &sl) {
     spd_status st = dev_alloc(ctx, &sl.mem, ctx->slot_bytes);
     if (st) return st;
     const uint64_t ldca_bytes = ctx->ldca_bytes;
-    if (ctx->sliding) {
+    if (ctx->at) {
+        sl.ldca_at = static_cast<uint8_t *>(sl.mem);
+        sl.seav_at = sl.ldca_at + ldca_bytes * 8;
+        SPD_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(sl.mem), ctx->slot_bytes / 4, 0u, nullptr));
+        sl.fresh = false;
+    } else if (ctx->sliding) {
         sl.ldca_ts = static_cast<uint16_t *>(sl.mem);
         sl.seav_ts = sl.ldca_ts + ldca_bytes * 8;
         SPD_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(sl.mem), ctx->slot_bytes / 4, 0u, nullptr));
@@ -1198,6 +1220,8 @@ spd_status ctx_create(const spd_params *p, uint32_t n_routers, uint32_t n_slots,
     ctx->budget = budget;
     ctx->sliding = p->window_slices > 0;
     ctx->K = p->window_slices;
+    ctx->at = ctx->sliding && p->sliding_counter == 0;
+    ctx->at_groups = ctx->at ? kAtPeriod - ctx->K : 0;
     default_tuning(&ctx->tune);
     if (hipGetDevice(&ctx->device) != hipSuccess) {
         delete ctx;
@@ -1249,8 +1273,10 @@ spd_status ctx_create(const spd_params *p, uint32_t n_routers, uint32_t n_slots,
     }
     ctx->seav_alloc = (ctx->d.seav_bytes + kSeavAlign - 1) / kSeavAlign * kSeavAlign;
     ctx->ldca_bytes = (ctx->d.ldca_words * 4 + 255) / 256 * 256;   // SEAV starts 256-byte aligned
-    // sliding: one 16-bit stamp per bit
-    ctx->slot_bytes = ctx->sliding ? (ctx->ldca_bytes * 16 + ctx->seav_alloc * 16) : (ctx->ldca_bytes + ctx->seav_alloc);
+    // sliding: one 16-bit stamp or one 8-bit AT counter per bit
+    ctx->slot_bytes = ctx->at        ? (ctx->ldca_bytes * 8 + ctx->seav_alloc * 8)
+                      : ctx->sliding ? (ctx->ldca_bytes * 16 + ctx->seav_alloc * 16)
+                                     : (ctx->ldca_bytes + ctx->seav_alloc);
     ctx->slots.resize(n_slots);
     for (auto &sl : ctx->slots) {
         st = slot_alloc(ctx, sl);
@@ -1443,7 +1469,13 @@ spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *st
         if (i0) src.push_back(static_cast<const uint32_t *>(g.mem));
         for (size_t i = i0; i < std::min(live.size(), i0 + kMaxGroup - 1); ++i)
             src.push_back(static_cast<const uint32_t *>(ctx->slots[live[i]].mem));
-        if (ctx->sliding) {
+        if (ctx->at) {
+            std::vector<const uint8_t *> s8;
+            for (auto q : src) s8.push_back(reinterpret_cast<const uint8_t *>(q));
+            ProfScope ps(ctx, SPD_K_MERGE, s);
+            SPD_HIP(ctx, launch_at_merge(static_cast<uint8_t *>(g.mem), s8.data(), (uint32_t)s8.size(), ctx->slot_bytes,
+                                         ctx->slice % kAtPeriod, s));
+        } else if (ctx->sliding) {
             std::vector<const uint16_t *> s16;
             for (auto q : src) s16.push_back(reinterpret_cast<const uint16_t *>(q));
             ProfScope ps(ctx, SPD_K_MERGE, s);
@@ -1488,12 +1520,40 @@ spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_ho
     return n > cap ? fail(ctx, SPD_E_TRUNCATED, "output capacity smaller than the number of super points") : SPD_OK;
 }
 
+spd_status spd_reset(spd_ctx *ctx, int32_t target, void *stream) {
+    if (!ctx) return SPD_E_INVALID;
+    Slot *sl = slot_of(ctx, target);
+    if (!sl) return fail(ctx, SPD_E_STATE, "bad target");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    order_stream(ctx, s);
+    if (ctx->sliding) return clear_slot(ctx, *sl, s);
+    sl->fresh = true;   // the next scan starts the slot from zero
+    sl->seav_zero = false;
+    return SPD_OK;
+}
+
 spd_status spd_slide(spd_ctx *ctx, void *stream) {
     if (!ctx) return SPD_E_INVALID;
     if (!ctx->sliding) return fail(ctx, SPD_E_STATE, "spd_slide needs a sliding-window context");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     order_stream(ctx, s);
+    if (ctx->at) {
+        // the next slice; then maintenance of one group of every pool (Section 5.2): its counters
+        // that are expired at the new slice are cleared
+        ctx->slice++;
+        const uint64_t chunk = (ctx->slot_bytes / ctx->at_groups + 15) / 16 * 16;
+        const uint64_t lo = (uint64_t)(ctx->slice % ctx->at_groups) * chunk;
+        const uint64_t hi = std::min(lo + chunk, ctx->slot_bytes);
+        if (lo < hi) {
+            std::vector<uint8_t *> pools;
+            for (auto &sl : ctx->slots) pools.push_back(static_cast<uint8_t *>(sl.mem));
+            ProfScope ps(ctx, SPD_K_FILL, s);
+            SPD_HIP(ctx, launch_at_sweep(pools.data(), (uint32_t)pools.size(), lo, hi, ctx->slice % kAtPeriod, ctx->K, s));
+        }
+        return SPD_OK;
+    }
     if (ctx->slice + 2 >= 0xFFFFu) {
         // stamps would overflow: shift them down so that the window keeps its bits
         const uint32_t next = ctx->slice + 1;
@@ -1533,13 +1593,16 @@ spd_status spd_export(spd_ctx *ctx, int32_t target, uint8_t *seav_host, uint32_t
     const int64_t lo = (int64_t)ctx->slice - (int64_t)ctx->K + 2;
     const uint16_t thr = (uint16_t)(lo < 1 ? 1 : lo);
     hipStream_t s = ctx->have_last ? ctx->last_stream : nullptr;
+    const uint32_t tm = ctx->slice % kAtPeriod;
     if (ldca_host) {
-        SPD_HIP(ctx, launch_bit_view(sl->ldca_ts, ctx->d.ldca_words * 32, thr, ctx->view, s));
+        if (ctx->at) SPD_HIP(ctx, launch_bit_view_at(sl->ldca_at, ctx->d.ldca_words * 32, tm, ctx->K, ctx->view, s));
+        else SPD_HIP(ctx, launch_bit_view(sl->ldca_ts, ctx->d.ldca_words * 32, thr, ctx->view, s));
         SPD_HIP(ctx, hipMemcpyAsync(ldca_host, ctx->view, ctx->d.ldca_words * 4, hipMemcpyDeviceToHost, s));
         SPD_HIP(ctx, hipStreamSynchronize(s));
     }
     if (seav_host) {
-        SPD_HIP(ctx, launch_bit_view(sl->seav_ts, ctx->seav_alloc * 8, thr, ctx->view, s));
+        if (ctx->at) SPD_HIP(ctx, launch_bit_view_at(sl->seav_at, ctx->seav_alloc * 8, tm, ctx->K, ctx->view, s));
+        else SPD_HIP(ctx, launch_bit_view(sl->seav_ts, ctx->seav_alloc * 8, thr, ctx->view, s));
         SPD_HIP(ctx, hipMemcpyAsync(seav_host, ctx->view, ctx->d.seav_bytes, hipMemcpyDeviceToHost, s));
         SPD_HIP(ctx, hipStreamSynchronize(s));
     }
@@ -1553,6 +1616,24 @@ spd_status spd_export_stamps(spd_ctx *ctx, int32_t target, uint16_t *seav_ts_hos
     if (!sl) return fail(ctx, SPD_E_STATE, "bad target");
     DeviceGuard dg(ctx->device);
     if (ctx->have_last) SPD_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
+    if (ctx->at) {
+        // rebuild 1 + last slice from each counter's age: last = slice - age
+        const uint32_t t = ctx->slice, tm = t % kAtPeriod;
+        auto decode = [&](const uint8_t *dev, uint64_t n, uint16_t *out) -> spd_status {
+            std::vector<uint8_t> raw(n);
+            SPD_HIP(ctx, hipMemcpy(raw.data(), dev, n, hipMemcpyDeviceToHost));
+            for (uint64_t i = 0; i < n; ++i) {
+                const uint32_t v = raw[i];
+                const uint32_t age = (tm + kAtPeriod + 1 - v) % kAtPeriod;
+                out[i] = v ? (uint16_t)(t - age + 1) : (uint16_t)0;
+            }
+            return SPD_OK;
+        };
+        spd_status st = SPD_OK;
+        if (seav_ts_host) st = decode(sl->seav_at, ctx->d.seav_bytes * 8, seav_ts_host);
+        if (!st && ldca_ts_host) st = decode(sl->ldca_at, ctx->d.ldca_words * 32, ldca_ts_host);
+        return st;
+    }
     if (seav_ts_host) SPD_HIP(ctx, hipMemcpy(seav_ts_host, sl->seav_ts, ctx->d.seav_bytes * 16, hipMemcpyDeviceToHost));
     if (ldca_ts_host) SPD_HIP(ctx, hipMemcpy(ldca_ts_host, sl->ldca_ts, ctx->d.ldca_words * 64, hipMemcpyDeviceToHost));
     return SPD_OK;
@@ -1949,6 +2030,14 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
         return st;
     }
     spd_ctx *ctx = S->ctx;
+    if (cfg->tuning) {
+        st = spd_set_tuning(ctx, cfg->tuning);
+        if (st) {
+            spd_server_destroy(S);
+            return st;
+        }
+    }
+    S->cfg.tuning = nullptr;   // the caller's struct is not kept
     DeviceGuard dg(ctx->device);
     // scratch for the largest fused group, reserved before the slots so admission never frees it
     BinGeometry g{};

@@ -70,6 +70,8 @@ class MethodParams:
     lr      LDCA rows
     log2lc  log2 of the LDCA columns
     window_slices   sliding window length in slices (Section 5); 0 = discrete window
+    sliding_counter the counter that replaces each bit under a sliding window: 0 = AT pool,
+                    1 = exact 16-bit time stamps (a storage choice; every result is the same)
     hash_seed       seed for the hash parameters
     """
     theta: int = 1024
@@ -80,6 +82,7 @@ class MethodParams:
     lr: int = 2
     log2lc: int = 16
     window_slices: int = 0
+    sliding_counter: int = 0
     hash_seed: int = 0x51A7E5EED
 
     def hashes(self) -> Tuple[List[int], List[int]]:

@@ -66,3 +66,20 @@ def heavy_hosts(rng, n_hosts, peers, noise=0):
     if noise:
         pairs = np.concatenate([pairs, random_pairs(rng, noise)])
     return pairs[rng.permutation(len(pairs))], hosts
+
+
+def oracle_sketch_threads(mp, parts, threads=8):
+    """The oracle's sketch of the union of `parts`, each part scanned by its own thread into a private
+    sketch, then OR-merged (the sketch depends only on the set of pairs)."""
+    import threading
+    p = oracle.params(mp)
+    sks = [oracle.Sketch(p) for _ in parts]
+    ths = [threading.Thread(target=s.scan, args=(np.ascontiguousarray(q),)) for s, q in zip(sks, parts)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    out = sks[0]
+    for s in sks[1:]:
+        out.merge(s)
+    return out

@@ -94,3 +94,14 @@ def test_derive_rejects_bad_parameters():
     p = spd.params_from(base.replace(r=20, sr=2), isb=[0, 5], ibn=[6, 7])
     d = spd.spd_derive(p)
     assert list(d.isb)[:2] == [0, 5] and list(d.ibn)[:2] == [6, 7]
+
+
+def test_ceilings_library_exports_its_declarations():
+    """The microbenchmark library of the hardware ceilings exports every call its header declares."""
+    import ctypes
+    with open(os.path.join(ROOT, "include", "spd_ceilings.h")) as f:
+        names = sorted(set(re.findall(r"^(?:int|uint32_t)\s+(spd_ceil_[a-z0-9_]+)\s*\(", f.read(), flags=re.M)))
+    assert len(names) == 5
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1901_07306_amd", "libspd_ceilings.so"))
+    for n in names:
+        assert hasattr(lib, n), n

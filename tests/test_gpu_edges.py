@@ -68,7 +68,8 @@ def test_sliding_stamps_renormalised():
     the library shifts every stamp down hold traffic.  Two routers; after every slice both routers'
     windows and their merge equal the oracle on the union of the last K slices."""
     K = 3
-    mp = st.MethodParams(theta=256, r=10, sr=4, a=2, log2k=10, lr=2, log2lc=8, window_slices=K, hash_seed=59)
+    mp = st.MethodParams(theta=256, r=10, sr=4, a=2, log2k=10, lr=2, log2lc=8, window_slices=K, sliding_counter=1,
+                         hash_seed=59)
     rng = np.random.default_rng(61)
     det = detector(mp, n_routers=2)
     try:
@@ -98,6 +99,46 @@ def test_sliding_stamps_renormalised():
             assert_same_report(det.close_window(spd.GLOBAL), union.detect(), f"merged slice {t}")
         # the stamps were shifted: the slice counter restarted near K
         assert spd.spd_current_slice(det.ctx) < 64
+    finally:
+        det.close()
+
+
+@pytest.mark.parametrize("K", [5, 60])
+def test_at_pool_across_code_periods(K):
+    """The AT pool stores slice codes modulo 255 and clears expired counters of one group of the pool
+    per slice.  Traffic in slices spread over more than three code periods, including slices whose
+    code repeats that of earlier traffic; after every slice with traffic, and after runs of empty
+    slices while that traffic expires, the bit view and the report of two routers and of their
+    merge must equal the oracle on the union of the last K slices."""
+    mp = st.MethodParams(theta=256, r=10, sr=4, a=2, log2k=10, lr=2, log2lc=8, window_slices=K, hash_seed=63)
+    rng = np.random.default_rng(65 + K)
+    busy = {0, 1, 2, 3, 200, 254, 255, 256, 257, 258, 510, 511, 700, 701, 702, 765, 766, 767}
+    check = busy | {t + d for t in busy for d in (K - 1, K, K + 1)} | {509, 764, 1020, 1021}
+    det = detector(mp, n_routers=2)
+    slices = {}
+    try:
+        log(f"case AT pool across code periods, K={K}")
+        for t in range(max(check) + 1):
+            if t:
+                det.slide()
+            if t in busy:
+                pairs, _ = heavy_hosts(rng, 3, int(rng.integers(200, 500)), noise=6000)
+                owner = rng.integers(0, 2, size=len(pairs))
+                det.scan_batches([(r, to_dev(pairs[owner == r])) for r in range(2)])
+                slices[t] = (pairs, owner)
+            if t not in check:
+                continue
+            live = [slices[j] for j in range(t - K + 1, t + 1) if j in slices]
+            for r in range(2):
+                parts = [p[o == r] for p, o in live] or [np.zeros((0, 2), np.uint32)]
+                union = oracle_sketch(mp, np.concatenate(parts))
+                assert_same_sketch(det, r, union, f"router {r} slice {t}")
+                assert_same_report(det.close_window(r), union.detect(), f"router {r} slice {t}")
+            det.merge([0, 1])
+            union = oracle_sketch(mp, np.concatenate([p for p, _ in live] or [np.zeros((0, 2), np.uint32)]))
+            assert_same_sketch(det, spd.GLOBAL, union, f"merged slice {t}")
+            assert_same_report(det.close_window(spd.GLOBAL), union.detect(), f"merged slice {t}")
+        assert spd.spd_current_slice(det.ctx) == max(check)
     finally:
         det.close()
 
@@ -171,3 +212,42 @@ def test_window_after_close_starts_from_zero(layout, other_stream):
         det.close()
         if s1 is not None:
             s1.synchronize()
+
+
+def test_reset_starts_a_new_window():
+    """spd_reset re-initialises a router's sketch without a report (a watch point's new window): a
+    merge then leaves it out and its next scan starts from zero; in sliding mode every stamp is
+    cleared."""
+    mp = st.CONFIGS["plain_1m"].params
+    rng = np.random.default_rng(91)
+    a0, _ = heavy_hosts(rng, 4, 2500, noise=120_000)
+    a1, _ = heavy_hosts(rng, 4, 2500, noise=120_000)
+    b0, _ = heavy_hosts(rng, 4, 2500, noise=120_000)
+    for layout in ("direct", "regions"):
+        log(f"case reset layout={layout}")
+        det = detector(mp, n_routers=2, **LAYOUTS[layout])
+        try:
+            det.scan(0, to_dev(a0))
+            det.scan(1, to_dev(a1))
+            det.reset(0)
+            det.merge([0, 1])
+            ref1 = oracle_sketch(mp, a1)
+            assert_same_sketch(det, spd.GLOBAL, ref1, "merge after reset")
+            det.scan(0, to_dev(b0))
+            assert_same_sketch(det, 0, oracle_sketch(mp, b0), "scan after reset")
+            assert_same_report(det.close_window(spd.GLOBAL), ref1.detect(), "global after reset")
+        finally:
+            det.close()
+    K = 3
+    ms = mp.replace(window_slices=K)
+    det = detector(ms)
+    try:
+        det.scan(0, to_dev(a0))
+        det.slide()
+        det.reset(0)
+        seav, ldca = det.export(0)
+        assert not seav.any() and not ldca.any()
+        det.scan(0, to_dev(b0))
+        assert_same_sketch(det, 0, oracle_sketch(mp, b0), "sliding scan after reset")
+    finally:
+        det.close()

@@ -281,11 +281,13 @@ def test_error_paths():
 
 
 # ------------------------------------------------------------------------------ sliding window
+@pytest.mark.parametrize("counter", ["at_pool", "stamps16"])
 @pytest.mark.parametrize("mode", ["one_router", "merged"])
-def test_sliding_window_parity(mode):
+def test_sliding_window_parity(mode, counter):
     K = 4
-    mp = st.MethodParams(theta=256, r=12, sr=4, a=2, log2k=10, lr=2, log2lc=8, window_slices=K, hash_seed=51)
-    log(f"case sliding {mode}")
+    mp = st.MethodParams(theta=256, r=12, sr=4, a=2, log2k=10, lr=2, log2lc=8, window_slices=K, hash_seed=51,
+                         sliding_counter=0 if counter == "at_pool" else 1)
+    log(f"case sliding {mode} {counter}")
     rng = np.random.default_rng(53)
     R = 1 if mode == "one_router" else 3
     det = detector(mp, n_routers=R, direct_max_pairs=0)
@@ -304,8 +306,17 @@ def test_sliding_window_parity(mode):
             assert spd.spd_current_slice(det.ctx) == t
             if mode == "one_router":
                 ts_seav, ts_ldca = det.export_stamps(0)
-                np.testing.assert_array_equal(ts_seav, sl[0].seav_ts)
-                np.testing.assert_array_equal(ts_ldca, sl[0].ldca_ts)
+                if counter == "stamps16":
+                    np.testing.assert_array_equal(ts_seav, sl[0].seav_ts)
+                    np.testing.assert_array_equal(ts_ldca, sl[0].ldca_ts)
+                else:
+                    # every counter left by maintenance holds the exact last slice, and every
+                    # counter active in the window is left
+                    for got_ts, want_ts in ((ts_seav, sl[0].seav_ts), (ts_ldca, sl[0].ldca_ts)):
+                        kept = got_ts != 0
+                        np.testing.assert_array_equal(got_ts[kept], want_ts[kept])
+                        live = want_ts >= max(1, t - K + 2)
+                        np.testing.assert_array_equal(got_ts[live], want_ts[live])
                 view = sl[0].bit_view(t)
                 assert_same_sketch(det, 0, view, f"slice {t}")
                 assert_same_report(det.close_window(0), view.detect(), f"slice {t} close")
