@@ -256,6 +256,7 @@ struct CloseArgs {
     uint32_t list_stride;
     uint32_t qcap;
     uint32_t stage_words;  // LDS words per wavefront holding one SEA (its bit view when sliding)
+    uint32_t parts_log2;   // each SEA's candidates are searched by 2^parts_log2 wavefronts
 };
 hipError_t launch_close(const Consts &c, const CloseArgs &a, int mode, uint32_t block, uint32_t grid, hipStream_t s);
 // Workgroups of the end-of-window kernel that one compute unit holds at once (registers and LDS).

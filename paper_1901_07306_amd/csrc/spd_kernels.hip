@@ -1605,6 +1605,11 @@ hipError_t launch_bit_view(const uint16_t *ts, uint64_t n_bits, uint16_t thr, ui
 }
 
 // ------------------------------------------------------------------------------ end of window
+// Bit view of the two 16-bit stamps packed in one 32-bit word (stamp j in half j).
+__device__ __forceinline__ uint32_t ts_bits2(uint32_t w, uint32_t thr) {
+    return ((w & 0xFFFFu) >= thr ? 1u : 0u) | ((w >> 16) >= thr ? 2u : 0u);
+}
+
 // Bit view of the four AT counters packed in one 32-bit word (counter j in byte j).
 __device__ __forceinline__ uint32_t at_bits4(uint32_t w, const CloseArgs &a) {
     return at_active(w & 0xFFu, a.at_tm, a.at_k) | at_active((w >> 8) & 0xFFu, a.at_tm, a.at_k) << 1 |
@@ -1617,8 +1622,8 @@ __device__ __forceinline__ uint32_t load_se(const CloseArgs &a, uint64_t byte) {
     if (MODE == kCloseBits) return a.seav[byte];
     uint32_t v = 0;
     if (MODE == kCloseStamps) {
-        const uint16_t *t = a.seav_ts + byte * 8;
-        for (uint32_t j = 0; j < 8; ++j) v |= (t[j] >= a.thr ? 1u : 0u) << j;
+        const u32x4 t = *reinterpret_cast<const u32x4 *>(a.seav_ts + byte * 8);   // 8 stamps
+        v = ts_bits2(t.x, a.thr) | ts_bits2(t.y, a.thr) << 2 | ts_bits2(t.z, a.thr) << 4 | ts_bits2(t.w, a.thr) << 6;
     } else {
         const uint64_t t = *reinterpret_cast<const uint64_t *>(a.seav_at + byte * 8);
         v = at_bits4((uint32_t)t, a) | at_bits4((uint32_t)(t >> 32), a) << 4;
@@ -1632,8 +1637,13 @@ __device__ __forceinline__ uint32_t load_ldc_word(const CloseArgs &a, uint32_t w
     if (MODE == kCloseBits) return a.ldca[word];
     uint32_t v = 0;
     if (MODE == kCloseStamps) {
-        const uint16_t *t = a.ldca_ts + (uint64_t)word * 32;
-        for (uint32_t j = 0; j < 32; ++j) v |= (t[j] >= a.thr ? 1u : 0u) << j;
+        const u32x4 *t = reinterpret_cast<const u32x4 *>(a.ldca_ts + (uint64_t)word * 32);   // 32 stamps
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            const u32x4 x = t[q];
+            v |= (ts_bits2(x.x, a.thr) | ts_bits2(x.y, a.thr) << 2 | ts_bits2(x.z, a.thr) << 4 |
+                  ts_bits2(x.w, a.thr) << 6) << (8 * q);
+        }
     } else {
         const u32x4 *t = reinterpret_cast<const u32x4 *>(a.ldca_at + (uint64_t)word * 32);
         const u32x4 x = t[0], y = t[1];
@@ -1657,9 +1667,47 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // ULDC of every queued candidate: AND of its LR LDCs, z0 = k - popcount; report if z0 <= z_theta.
 // Four candidates at a time, 16 lanes each; a lane reads 8 words of each of two LDCs before it
 // waits, so one round trip to memory serves four candidates (k = 4096, LR = 2).
+// Counter modes (a window of time stamps or AT counters): an LDC word is 32 counters (64 or 32
+// bytes), so one candidate takes the whole wavefront: each lane reads two words of every row, all
+// rows' loads in flight together (one round trip per candidate for k up to 4096).
+template <int MODE>
+__device__ void filter_queue_counters(const CloseArgs &a, const Consts &c, const uint32_t *queue, uint32_t qn,
+                                      uint32_t lane) {
+    const uint32_t words = 1u << (c.log2k - 5);
+    for (uint32_t e = 0; e < qn; ++e) {
+        const uint32_t h = queue[e];
+        uint32_t ones = 0;
+        for (uint32_t w0 = 0; w0 < words; w0 += 128) {
+            const uint32_t wa = w0 + lane, wb = w0 + 64 + lane;
+            uint32_t ua = 0xFFFFFFFFu, ub = 0xFFFFFFFFu;
+#pragma unroll
+            for (uint32_t r = 0; r < (uint32_t)kMaxRows; ++r) {
+                if (r >= c.lr) continue;
+                const uint32_t base = ((r << c.log2lc) | ldc_col(h, r, c)) << (c.log2k - 5);
+                ua &= load_ldc_word<MODE>(a, base + (wa < words ? wa : words - 1));
+                ub &= load_ldc_word<MODE>(a, base + (wb < words ? wb : words - 1));
+            }
+            ones += (wa < words ? __popc(ua) : 0u) + (wb < words ? __popc(ub) : 0u);
+        }
+        ones = wave_sum(ones);
+        const uint32_t z0 = (1u << c.log2k) - ones;
+        if (lane == 0 && z0 <= c.z_theta) {
+            const uint32_t slot = atomicAdd(&a.counters[0], 1u);
+            if (slot < a.rec_cap) {
+                a.rec[2 * slot] = h;
+                a.rec[2 * slot + 1] = z0;
+            }
+        }
+    }
+}
+
 template <int MODE>
 __device__ void filter_queue(const CloseArgs &a, const Consts &c, const uint32_t *queue, uint32_t qn, uint32_t lane) {
-    constexpr uint32_t G = 16, W = MODE == kCloseBits ? 8 : MODE == kCloseStamps ? 2 : 1, RB = MODE != kCloseBits ? 1 : 2;
+    if (MODE != kCloseBits) {
+        filter_queue_counters<MODE>(a, c, queue, qn, lane);
+        return;
+    }
+    constexpr uint32_t G = 16, W = 8, RB = 2;
     const uint32_t words = 1u << (c.log2k - 5);
     const uint32_t grp = lane / G, sub = lane % G;
     for (uint32_t e0 = 0; e0 < qn; e0 += 64 / G) {
@@ -1716,8 +1764,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t lmask = (c.L == 32) ? 0xFFFFFFFFull : ((1ull << c.L) - 1ull);
     uint32_t n_cand = 0;
+    // work items: (SEA, part); the 2^parts_log2 parts of a SEA take interleaved shares of its tuples
+    // (or of its LPs), so they find disjoint candidates
+    const uint32_t P = 1u << a.parts_log2, part_mask = P - 1u;
+    const uint64_t n_items = (uint64_t)a.n_rp << a.parts_log2;
 
-    for (uint32_t rp = blockIdx.x * NW + wid; rp < a.n_rp; rp += gridDim.x * NW) {
+    for (uint64_t wi = (uint64_t)blockIdx.x * NW + wid; wi < n_items; wi += (uint64_t)gridDim.x * NW) {
+        const uint32_t rp = (uint32_t)(wi >> a.parts_log2), part = (uint32_t)wi & part_mask;
         const uint64_t sea = (uint64_t)rp * c.sea_bytes;
         // stage the whole SEA in LDS (when it fits), eight loads in flight per lane
         auto se_at = [&](uint32_t byte) -> uint32_t { return staged ? sea8[byte] : load_se<MODE>(a, sea + byte); };
@@ -1767,7 +1820,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
             // round by adding the digits of 64, computed once per SEA: no division in the loop.
             uint32_t dg[kMaxRows], st[kMaxRows];
             {
-                uint32_t rem = lane, inc = 64;
+                uint32_t rem = part * 64u + lane, inc = 64u * P;
 #pragma unroll
                 for (uint32_t i = 0; i < (uint32_t)kMaxRows; ++i) {
                     dg[i] = rem % cnt[i];
@@ -1776,7 +1829,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                     inc /= cnt[i];
                 }
             }
-            for (uint64_t u0 = 0; u0 < total; u0 += 64) {
+            for (uint64_t u0 = (uint64_t)part * 64u; u0 < total; u0 += 64u * P) {
                 const uint64_t u = u0 + lane;
                 bool cand = false;
                 uint32_t h = 0;
@@ -1802,7 +1855,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                         h = (uint32_t)(((uint64_t)lp << c.r) | rp);
                     }
                 }
-                // advance the digits by 64; each sum stays below twice its radix, so it wraps at
+                // advance the digits by 64 P; each sum stays below twice its radix, so it wraps at
                 // most once (rows past the row count have radix 1 and stay 0)
                 uint32_t carry = 0;
 #pragma unroll
@@ -1823,7 +1876,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
             }
         } else {
             // more tuples than hosts in this SEA: test every LP directly (the candidate definition)
-            for (uint64_t l0 = 0; l0 <= lmask; l0 += 64) {
+            for (uint64_t l0 = (uint64_t)part * 64u; l0 <= lmask; l0 += 64u * P) {
                 const uint64_t l = l0 + lane;
                 bool cand = false;
                 if (l <= lmask) {

@@ -1069,12 +1069,16 @@ spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArg
     if ((b / 64) * per_wave * 4ull > kMaxLds)
         return fail(ctx, SPD_E_INVALID, "SEA rows too large for the end-of-window kernel");
     const uint32_t waves = b / 64;
-    const uint64_t want = ((uint64_t)a->n_rp + waves - 1) / waves;
     *block = b;
-    // one round of resident workgroups; each wavefront then takes SEAs round robin
+    // one round of resident workgroups; each wavefront then takes (SEA, part) items round robin.
+    // With fewer SEAs than resident wavefronts, each SEA's candidate search is split into parts
+    // (a power of two, at most 64) so that every wavefront has work.
     if (!ctx->close_per_cu[b / 128])
         ctx->close_per_cu[b / 128] = close_blocks_per_cu(close_mode(ctx), b, (uint32_t)((b / 64) * per_wave * 4));
     const uint64_t resident = (uint64_t)ctx->n_cu * ctx->close_per_cu[b / 128];
+    a->parts_log2 = 0;
+    while (a->parts_log2 < 6 && ((uint64_t)a->n_rp << (a->parts_log2 + 1)) <= resident * waves) a->parts_log2++;
+    const uint64_t want = (((uint64_t)a->n_rp << a->parts_log2) + waves - 1) / waves;
     *grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, resident));
     return SPD_OK;
 }
