@@ -36,6 +36,9 @@ def candidate_settings(quick: bool = False) -> List[dict]:
                 dict(bin_mode=2, bucket_bits=20, tile_pairs=8192, bin_block=512, apply_block=1024, apply_unroll=16),
                 dict(bin_mode=2, bucket_bits=20, tile_pairs=16384, bin_block=1024, apply_block=1024, apply_unroll=16),
                 dict(bin_mode=2, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024, apply_unroll=32),
+                dict(bin_mode=2, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=512, apply_unroll=16),
+                dict(bin_mode=2, bucket_bits=20, tile_pairs=4096, bin_block=1024, apply_block=1024, apply_unroll=16),
+                dict(bin_mode=2, bucket_bits=20, tile_pairs=4096, bin_block=512, apply_block=1024, apply_unroll=16),
                 dict(bin_mode=1, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024, apply_unroll=16),
                 dict(bin_mode=0, bucket_bits=20, tile_pairs=16384, bin_block=1024, apply_block=1024, apply_unroll=16)]
     out = []
