@@ -218,12 +218,9 @@ def bench_routers(spd, torch, np, st, at, steps, warmup):
     R = w.n_routers
     xs = [torch.from_numpy(p.view(np.int32)).to("cuda") for p in win.pairs]
     params = spd.params_from(w.params)
-    probe = spd.Detector(params)
-    tuned = at.autotune(probe, xs[0], quick=True)
-    probe.close()
     det = spd.Detector(params, n_routers=R)
-    set_tuning(det, tuned)
     batches = [(r, xs[r]) for r in range(R)]
+    tuned = at.autotune(det, xs[0], quick=True, batches=batches)   # timed on the fused call itself
 
     def step():
         det.scan_batches(batches)
@@ -509,6 +506,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter collection: 2 windows + one 512 MiB copy for scaling")
+    ap.add_argument("--pmc-workload", default="plain_64m", choices=["plain_64m", "sliding_300x1m"],
+                    help="--pmc-run on the sliding workload: its first 64 slices, each scanned and reported")
     ap.add_argument("--configs", default="plain_1m,routers_8x16m,sliding_300x1m",
                     help="other workloads to measure (comma list; empty: none)")
     ap.add_argument("--serving-windows", type=int, default=8, help="windows per router in the serving run (0: skip)")
@@ -536,6 +535,19 @@ def main() -> int:
         return 2
     if args.ceilings:
         print(json.dumps(ceilings(torch)), flush=True)
+        return 0
+    if args.pmc_run and args.pmc_workload == "sliding_300x1m":
+        ws = st.CONFIGS["sliding_300x1m"]
+        tr = st.gen_sliding(ws)
+        det = spd.Detector(spd.params_from(ws.params))
+        for t in range(64):
+            if t:
+                det.slide()
+            det.scan(0, torch.from_numpy(tr.slice(t).view(np.int32)).to("cuda"))
+            det.close_window(0)
+        torch.cuda.synchronize()
+        det.close()
+        log("pmc run done: 64 sliding slices")
         return 0
     w = st.CONFIGS["plain_64m"]
     log(f"generating {w.name}: {w.n_packets} pairs")

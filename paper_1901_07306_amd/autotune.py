@@ -18,13 +18,22 @@ TUNED_FIELDS = ("bin_mode", "bucket_bits", "tile_pairs", "bin_block", "apply_blo
                 "direct_block", "direct_grid_per_cu", "seav_lds", "direct_max_pairs")
 
 
-def _scan_ms(det, x, reps: int) -> float:
+def _scan_ms(det, x, reps: int, batches=None) -> float:
+    """Device time of one scan of x into router 0, or of one fused call over `batches`
+    ((router, tensor) pairs), averaged over reps; the routers are reset afterwards."""
     det.profile_enable(True)
     for _ in range(reps):
-        det.scan(0, x)
+        if batches:
+            det.scan_batches(batches)
+        else:
+            det.scan(0, x)
     prof = det.profile()
     det.profile_enable(False)
-    det.close_window(0)
+    if batches:
+        for r in sorted({b[0] for b in batches}):
+            det.reset(r)
+    else:
+        det.close_window(0)
     return sum(prof[k][1] for k in SCAN_KINDS) / reps
 
 
@@ -54,8 +63,9 @@ def _apply(det, settings: dict) -> None:
     det.tuning = t
 
 
-def tune_binned(det, x, reps: int = 3, quick: bool = False) -> Tuple[dict, List[Tuple[dict, float]]]:
-    """Fastest binned-scan setting for batch x on detector det (router 0 is used and reset)."""
+def tune_binned(det, x, reps: int = 3, quick: bool = False, batches=None) -> Tuple[dict, List[Tuple[dict, float]]]:
+    """Fastest binned-scan setting for batch x on detector det (router 0 is used and reset), or for
+    the fused call over `batches` when given (the routers named there are reset)."""
     base = det.tuning
     table = []
     for cand in candidate_settings(quick):
@@ -63,8 +73,8 @@ def tune_binned(det, x, reps: int = 3, quick: bool = False) -> Tuple[dict, List[
             _apply(det, dict(cand, direct_max_pairs=0))
         except Exception:
             continue
-        _scan_ms(det, x, 1)   # warm-up (scratch growth)
-        table.append((cand, _scan_ms(det, x, reps)))
+        _scan_ms(det, x, 1, batches)   # warm-up (scratch growth)
+        table.append((cand, _scan_ms(det, x, reps, batches)))
     det.tuning = base
     best = min(table, key=lambda e: e[1])[0]
     return best, table
@@ -105,13 +115,15 @@ def crossover(det, x, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22), reps:
     return best
 
 
-def autotune(det, x, key: Optional[tuple] = None, quick: bool = False) -> dict:
-    """Tune det for batches like x and apply the result.  Returns the chosen settings; the timing
-    tables are kept in the cache entry (``last_tables(key)``)."""
+def autotune(det, x, key: Optional[tuple] = None, quick: bool = False, batches=None) -> dict:
+    """Tune det for batches like x and apply the result.  With `batches` ((router, tensor) pairs of
+    one fused call), the binned settings are those of that fused call; the direct kernel's shape and
+    the direct/binned crossover are still tuned on x.  Returns the chosen settings; the timing tables
+    are kept in the cache entry (``last_tables(key)``)."""
     import torch
-    key = key or cache_key(det, x)
+    key = key or cache_key(det, x, batches)
     if key not in _CACHE:
-        b, tb = tune_binned(det, x, quick=quick)
+        b, tb = tune_binned(det, x, quick=quick, batches=batches)
         d, td = tune_direct(det, x[: min(x.shape[0], 1 << 20)])
         cross = crossover(det, x)
         _CACHE[key] = dict(settings=dict(b, **d, direct_max_pairs=cross), binned=tb, direct=td,
@@ -120,11 +132,12 @@ def autotune(det, x, key: Optional[tuple] = None, quick: bool = False) -> dict:
     return dict(_CACHE[key]["settings"])
 
 
-def cache_key(det, x) -> tuple:
+def cache_key(det, x, batches=None) -> tuple:
     import torch
     p = det.params
+    fused = tuple((int(r), int(t.shape[0])) for r, t in batches) if batches else ()
     return (torch.cuda.get_device_name(0), tuple(p.hash_mul[:3]), p.r, p.sr, p.log2k, p.lr, p.log2lc,
-            int(x.shape[0]))
+            int(x.shape[0]), fused)
 
 
 def last_tables(key: tuple) -> dict:

@@ -1680,9 +1680,8 @@ __device__ void filter_queue_counters(const CloseArgs &a, const Consts &c, const
         for (uint32_t w0 = 0; w0 < words; w0 += 128) {
             const uint32_t wa = w0 + lane, wb = w0 + 64 + lane;
             uint32_t ua = 0xFFFFFFFFu, ub = 0xFFFFFFFFu;
-#pragma unroll
-            for (uint32_t r = 0; r < (uint32_t)kMaxRows; ++r) {
-                if (r >= c.lr) continue;
+            // a runtime loop over the rows keeps the decoding code small (instruction cache)
+            for (uint32_t r = 0; r < c.lr; ++r) {
                 const uint32_t base = ((r << c.log2lc) | ldc_col(h, r, c)) << (c.log2k - 5);
                 ua &= load_ldc_word<MODE>(a, base + (wa < words ? wa : words - 1));
                 ub &= load_ldc_word<MODE>(a, base + (wb < words ? wb : words - 1));

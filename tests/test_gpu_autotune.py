@@ -70,3 +70,27 @@ def test_autotune_choice_is_applied_and_exact():
         assert_same_report(det.close_window(0), ref.detect(), "tuned")
     finally:
         det.close()
+
+
+def test_autotune_on_a_fused_call():
+    """Tuning on the fused call of two routers' batches: the choice is applied and the sketches of
+    both routers still equal the oracle's."""
+    mp = PARAMS["plain_1m"]
+    rng = np.random.default_rng(4021)
+    p0, _ = heavy_hosts(rng, 4, 2500, noise=700_000)
+    p1, _ = heavy_hosts(rng, 4, 2500, noise=500_000)
+    x0, x1 = to_dev(p0), to_dev(p1)
+    det = spd.Detector(spd.params_from(mp), n_routers=2)
+    try:
+        log("case autotune on a fused call of two routers")
+        chosen = autotune.autotune(det, x0, quick=True, batches=[(0, x0), (1, x1)])
+        t = det.tuning
+        for k, v in chosen.items():
+            assert getattr(t, k) == v, k
+        det.scan_batches([(0, x0), (1, x1)])
+        for r, p in ((0, p0), (1, p1)):
+            ref = oracle_sketch(mp, p)
+            assert_same_sketch(det, r, ref, f"router {r}")
+            assert_same_report(det.close_window(r), ref.detect(), f"router {r}")
+    finally:
+        det.close()
