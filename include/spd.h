@@ -225,8 +225,10 @@ spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_ho
  * `stream`. */
 spd_status spd_reset(spd_ctx *ctx, int32_t target, void *stream);
 
-/* Sliding mode only: the next scans belong to the next time slice (Section 5.2).  Stamps older
- * than the window simply drop out of the bit view; no state is rewritten. */
+/* Sliding mode only: the next scans belong to the next time slice (Section 5.2).  Exact stamps
+ * older than the window simply drop out of the bit view.  With the AT pool, one of 255 - K groups
+ * of every slot's counters is maintained, enqueued on `stream`: its counters outside the window
+ * get the code of slice t - K, so that every counter's age read modulo 256 stays exact. */
 spd_status spd_slide(spd_ctx *ctx, void *stream);
 
 /* Copy a target's sketch to host memory in the canonical layouts (seav_host: seav_bytes bytes,
@@ -239,7 +241,7 @@ spd_status spd_import(spd_ctx *ctx, int32_t target, const uint8_t *seav_host, co
 /* Sliding mode: copy a target's raw time stamps (1 + last slice that set the bit, 0 = never):
  * seav_ts_host holds seav_bytes * 8 entries (bit b of byte x at 8x + b), ldca_ts_host holds
  * ldca_words * 32 entries (one per LDCA bit).  With the AT pool the stamps are rebuilt from the
- * counters (modulo 2^16); a counter that maintenance has cleared (set more than K slices ago)
+ * counters (modulo 2^16); a counter outside the window (set K or more slices ago, or never)
  * reads 0. */
 spd_status spd_export_stamps(spd_ctx *ctx, int32_t target, uint16_t *seav_ts_host, uint16_t *ldca_ts_host);
 

@@ -87,19 +87,23 @@ struct SlotPtrs {
     uint8_t *ldca_at;
 };
 
-// Sliding window with the AT pool: every bit is an 8-bit counter, 0 = never set, else 1 + (the
-// last slice that set it mod kAtPeriod).  At slice t a counter v != 0 is active (bit 1) iff its
-// age ((t - (v - 1)) mod kAtPeriod) is below K.  Maintenance at every slice start clears the
-// expired counters of one of G = kAtPeriod - K groups of the pool, so each counter is swept at
-// least once every G slices and its true age stays below K + G = kAtPeriod while it is nonzero:
-// the age read modulo kAtPeriod is then the true age.
-constexpr uint32_t kAtPeriod = 255;
-__host__ __device__ __forceinline__ uint32_t at_code(uint32_t slice) { return slice % kAtPeriod + 1u; }
-__device__ __forceinline__ uint32_t at_active(uint32_t v, uint32_t tm, uint32_t K) {
-    int d = (int)tm - (int)v + 1;   // tm = t mod kAtPeriod
-    d += d < 0 ? (int)kAtPeriod : 0;
-    return (v != 0u && (uint32_t)d < K) ? 1u : 0u;
+// Sliding window with the AT pool: every bit is an 8-bit counter holding the code (slice mod 256)
+// of a slice: the last slice that set it, or, once that is older than the window, a slice that is
+// just outside it.  At slice t a counter v is active (bit 1) iff its age (t - v) mod 256 is below
+// K.  Maintenance at every slice start re-stamps the expired counters of one of G = 255 - K groups
+// of the pool with the code of slice t - K, so each counter is visited at least once every G
+// slices and its true age stays below K + G = 255 < 256: the age read modulo 256 is the true age
+// (never-set counters start with the code of slice -K, already expired).
+constexpr uint32_t kAtCodes = 256;
+__host__ __device__ __forceinline__ uint32_t at_code(uint32_t slice) { return slice & (kAtCodes - 1u); }
+// An expired code at slice t: that of slice t - K.
+__host__ __device__ __forceinline__ uint32_t at_expired_code(uint32_t slice, uint32_t K) {
+    return (slice - K) & (kAtCodes - 1u);
 }
+__host__ __device__ __forceinline__ uint32_t at_active(uint32_t v, uint32_t ct, uint32_t K) {
+    return ((ct - v) & (kAtCodes - 1u)) < K ? 1u : 0u;   // ct = at_code(t)
+}
+constexpr uint32_t kAtMaxK = 254;   // G = 255 - K >= 1
 
 // What the end-of-window kernel reads: bits, 16-bit time stamps, or AT counters.
 enum CloseMode : int { kCloseBits = 0, kCloseStamps = 1, kCloseAt = 2 };
@@ -141,15 +145,15 @@ hipError_t launch_scan_direct(const Consts &c, const BatchDesc *batches, uint32_
 // code when at is set).
 hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
                              uint32_t value, bool at, uint32_t block, uint32_t grid, hipStream_t s);
-// AT pool maintenance: clears the counters of bytes [lo, hi) of each of n pools (hi <= pool bytes,
-// lo and hi multiples of 16) that are expired at the slice whose code is tm + 1.
-hipError_t launch_at_sweep(uint8_t *const *pools, uint32_t n, uint64_t lo, uint64_t hi, uint32_t tm, uint32_t K,
+// AT pool maintenance: the counters of bytes [lo, hi) of each of n pools (hi <= pool bytes, lo and
+// hi multiples of 16) that are expired at the slice of code ct are set to that slice's expired code.
+hipError_t launch_at_sweep(uint8_t *const *pools, uint32_t n, uint64_t lo, uint64_t hi, uint32_t ct, uint32_t K,
                            hipStream_t s);
 // dst = per counter the most recent of the n_src pools (the AT version of the OR merge).
-hipError_t launch_at_merge(uint8_t *dst, const uint8_t *const *src, uint32_t n_src, uint64_t n_bytes, uint32_t tm,
+hipError_t launch_at_merge(uint8_t *dst, const uint8_t *const *src, uint32_t n_src, uint64_t n_bytes, uint32_t ct,
                            hipStream_t s);
 // Bit view of AT counters: bit j of word w is 1 iff counter 32 w + j is active.
-hipError_t launch_bit_view_at(const uint8_t *at, uint64_t n_bits, uint32_t tm, uint32_t K, uint32_t *out_words,
+hipError_t launch_bit_view_at(const uint8_t *at, uint64_t n_bits, uint32_t ct, uint32_t K, uint32_t *out_words,
                               hipStream_t s);
 hipError_t launch_bin(const Consts &c, const BinGeometry &g, const BatchDesc *batches, uint32_t n_batches,
                       uint32_t n_tiles, uint32_t *items, uint32_t *meta, const SlotPtrs *slots, hipStream_t s);
@@ -247,7 +251,7 @@ struct CloseArgs {
     const uint8_t *seav_at;
     const uint8_t *ldca_at;
     uint32_t thr;        // sliding, 16-bit stamps: stamp threshold of the bit view
-    uint32_t at_tm;      // sliding, AT pool: current slice mod kAtPeriod
+    uint32_t at_ct;      // sliding, AT pool: code of the current slice
     uint32_t at_k;       // sliding, AT pool: window length K
     uint32_t *rec;       // (ip, z0) pairs
     uint32_t *counters;  // [0] reported, [1] candidates

@@ -256,25 +256,30 @@ struct CPoolTable {
 // Byte k of a 16-byte vector.
 __device__ __forceinline__ uint32_t byte_of(const u32x4 &v, uint32_t k) { return (v[k >> 2] >> (8 * (k & 3))) & 0xFFu; }
 
-__global__ __launch_bounds__(256) void k_at_sweep(PoolTable pt, uint32_t n, uint64_t lo16, uint64_t hi16, uint32_t tm,
+__global__ __launch_bounds__(256) void k_at_sweep(PoolTable pt, uint32_t n, uint64_t lo16, uint64_t hi16, uint32_t ct,
                                                   uint32_t K) {
     const uint64_t stride = (uint64_t)gridDim.x * 256;
+    const uint32_t ex = (ct - K) & (kAtCodes - 1u);   // the code of slice t - K: expired, age K
     for (uint32_t k = 0; k < n; ++k) {
         u32x4 *p = reinterpret_cast<u32x4 *>(pt.p[k]);
         for (uint64_t i = lo16 + blockIdx.x * (uint64_t)256 + threadIdx.x; i < hi16; i += stride) {
             const u32x4 v = p[i];
-            u32x4 o = {0u, 0u, 0u, 0u};
+            u32x4 o = v;
+            bool changed = false;
 #pragma unroll
             for (uint32_t b = 0; b < 16; ++b) {
                 const uint32_t x = byte_of(v, b);
-                if (at_active(x, tm, K)) o[b >> 2] |= x << (8 * (b & 3));
+                if (!at_active(x, ct, K) && x != ex) {
+                    o[b >> 2] = (o[b >> 2] & ~(0xFFu << (8 * (b & 3)))) | (ex << (8 * (b & 3)));
+                    changed = true;
+                }
             }
-            if (o.x != v.x || o.y != v.y || o.z != v.z || o.w != v.w) p[i] = o;
+            if (changed) p[i] = o;
         }
     }
 }
 
-hipError_t launch_at_sweep(uint8_t *const *pools, uint32_t n, uint64_t lo, uint64_t hi, uint32_t tm, uint32_t K,
+hipError_t launch_at_sweep(uint8_t *const *pools, uint32_t n, uint64_t lo, uint64_t hi, uint32_t ct, uint32_t K,
                            hipStream_t s) {
     if (lo % 16 || hi % 16 || hi < lo) return hipErrorInvalidValue;
     for (uint32_t k0 = 0; k0 < n; k0 += kMaxGroup) {
@@ -284,58 +289,46 @@ hipError_t launch_at_sweep(uint8_t *const *pools, uint32_t n, uint64_t lo, uint6
         const uint64_t vec = (hi - lo) / 16;
         if (vec == 0) return hipSuccess;
         const uint32_t grid = (uint32_t)((vec + 255) / 256 < 2048 ? (vec + 255) / 256 : 2048);
-        hipLaunchKernelGGL(k_at_sweep, dim3(grid), dim3(256), 0, s, pt, m, lo / 16, hi / 16, tm, K);
+        hipLaunchKernelGGL(k_at_sweep, dim3(grid), dim3(256), 0, s, pt, m, lo / 16, hi / 16, ct, K);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// Per counter, the most recent of the sources: the smallest age among nonzero counters.  Every
-// source is maintained, so every nonzero age read modulo kAtPeriod is the true age.
+// Per counter, the most recent of the sources: the smallest age.  Every source is maintained, so
+// every age read modulo 256 is the true age.
 __global__ __launch_bounds__(256) void k_at_merge(uint8_t *__restrict__ dst, CPoolTable src, uint32_t n_src,
-                                                  uint64_t n16, uint32_t tm) {
+                                                  uint64_t n16, uint32_t ct) {
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     for (uint64_t i = blockIdx.x * (uint64_t)256 + threadIdx.x; i < n16; i += stride) {
-        uint32_t best[16], age[16];
-#pragma unroll
-        for (uint32_t b = 0; b < 16; ++b) {
-            best[b] = 0u;
-            age[b] = kAtPeriod;
-        }
-        for (uint32_t k = 0; k < n_src; ++k) {
+        u32x4 best = reinterpret_cast<const u32x4 *>(src.p[0])[i];
+        for (uint32_t k = 1; k < n_src; ++k) {
             const u32x4 v = reinterpret_cast<const u32x4 *>(src.p[k])[i];
 #pragma unroll
             for (uint32_t b = 0; b < 16; ++b) {
-                const uint32_t x = byte_of(v, b);
-                int d = (int)tm - (int)x + 1;
-                d += d < 0 ? (int)kAtPeriod : 0;
-                if (x != 0u && (uint32_t)d < age[b]) {
-                    age[b] = (uint32_t)d;
-                    best[b] = x;
-                }
+                const uint32_t x = byte_of(v, b), y = byte_of(best, b);
+                if (((ct - x) & (kAtCodes - 1u)) < ((ct - y) & (kAtCodes - 1u)))
+                    best[b >> 2] = (best[b >> 2] & ~(0xFFu << (8 * (b & 3)))) | (x << (8 * (b & 3)));
             }
         }
-        u32x4 o = {0u, 0u, 0u, 0u};
-#pragma unroll
-        for (uint32_t b = 0; b < 16; ++b) o[b >> 2] |= best[b] << (8 * (b & 3));
-        reinterpret_cast<u32x4 *>(dst)[i] = o;
+        reinterpret_cast<u32x4 *>(dst)[i] = best;
     }
 }
 
-hipError_t launch_at_merge(uint8_t *dst, const uint8_t *const *src, uint32_t n_src, uint64_t n_bytes, uint32_t tm,
+hipError_t launch_at_merge(uint8_t *dst, const uint8_t *const *src, uint32_t n_src, uint64_t n_bytes, uint32_t ct,
                            hipStream_t s) {
     if (n_src == 0 || n_src > (uint32_t)kMaxGroup || n_bytes % 16) return hipErrorInvalidValue;
     CPoolTable t{};
     for (uint32_t k = 0; k < n_src; ++k) t.p[k] = src[k];
     const uint64_t n16 = n_bytes / 16;
     const uint32_t grid = (uint32_t)((n16 + 255) / 256 < 8192 ? (n16 + 255) / 256 : 8192);
-    hipLaunchKernelGGL(k_at_merge, dim3(grid ? grid : 1), dim3(256), 0, s, dst, t, n_src, n16, tm);
+    hipLaunchKernelGGL(k_at_merge, dim3(grid ? grid : 1), dim3(256), 0, s, dst, t, n_src, n16, ct);
     return hipGetLastError();
 }
 
 // Bit view of AT counters: 32 counters (two 16-byte vectors) per output word.
-__global__ __launch_bounds__(256) void k_bit_view_at(const uint8_t *__restrict__ at, uint64_t n_words, uint32_t tm,
+__global__ __launch_bounds__(256) void k_bit_view_at(const uint8_t *__restrict__ at, uint64_t n_words, uint32_t ct,
                                                      uint32_t K, uint32_t *__restrict__ out) {
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     for (uint64_t w = blockIdx.x * (uint64_t)256 + threadIdx.x; w < n_words; w += stride) {
@@ -343,19 +336,19 @@ __global__ __launch_bounds__(256) void k_bit_view_at(const uint8_t *__restrict__
         uint32_t v = 0;
 #pragma unroll
         for (uint32_t j = 0; j < 16; ++j) {
-            v |= at_active(byte_of(a, j), tm, K) << j;
-            v |= at_active(byte_of(b, j), tm, K) << (16 + j);
+            v |= at_active(byte_of(a, j), ct, K) << j;
+            v |= at_active(byte_of(b, j), ct, K) << (16 + j);
         }
         out[w] = v;
     }
 }
 
-hipError_t launch_bit_view_at(const uint8_t *at, uint64_t n_bits, uint32_t tm, uint32_t K, uint32_t *out_words,
+hipError_t launch_bit_view_at(const uint8_t *at, uint64_t n_bits, uint32_t ct, uint32_t K, uint32_t *out_words,
                               hipStream_t s) {
     if (n_bits % 32) return hipErrorInvalidValue;
     const uint64_t words = n_bits / 32;
     const uint32_t grid = (uint32_t)((words + 255) / 256 < 8192 ? (words + 255) / 256 : 8192);
-    hipLaunchKernelGGL(k_bit_view_at, dim3(grid ? grid : 1), dim3(256), 0, s, at, words, tm, K, out_words);
+    hipLaunchKernelGGL(k_bit_view_at, dim3(grid ? grid : 1), dim3(256), 0, s, at, words, ct, K, out_words);
     return hipGetLastError();
 }
 
@@ -1610,10 +1603,22 @@ __device__ __forceinline__ uint32_t ts_bits2(uint32_t w, uint32_t thr) {
     return ((w & 0xFFFFu) >= thr ? 1u : 0u) | ((w >> 16) >= thr ? 2u : 0u);
 }
 
-// Bit view of the four AT counters packed in one 32-bit word (counter j in byte j).
-__device__ __forceinline__ uint32_t at_bits4(uint32_t w, const CloseArgs &a) {
-    return at_active(w & 0xFFu, a.at_tm, a.at_k) | at_active((w >> 8) & 0xFFu, a.at_tm, a.at_k) << 1 |
-           at_active((w >> 16) & 0xFFu, a.at_tm, a.at_k) << 2 | at_active(w >> 24, a.at_tm, a.at_k) << 3;
+// Activity of the four AT counters packed in one 32-bit word, four at a time (SIMD within a
+// register): bit 7 of byte j of the result is set iff counter j is active, i.e. its age
+// (ct - v) mod 256 is below K.  The per-byte difference is taken without borrows between bytes;
+// the per-byte compare with K needs K <= 128, so larger windows decode byte by byte.
+__device__ __forceinline__ uint32_t at_active4(uint32_t w, const CloseArgs &a) {
+    constexpr uint32_t H = 0x80808080u, L = 0x7F7F7F7Fu;
+    if (a.at_k <= 128u) {
+        const uint32_t ct4 = a.at_ct * 0x01010101u, k4 = a.at_k * 0x01010101u;
+        const uint32_t e = ((ct4 | H) - (w & L)) ^ ((ct4 ^ ~w) & H);   // (ct - v) mod 256 per byte
+        const uint32_t d = ((e & L) | H) - k4;                          // top bit: low 7 bits of e >= K
+        return ~(e | d) & H;
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) r |= at_active((w >> (8 * j)) & 0xFFu, a.at_ct, a.at_k) << (8 * j + 7);
+    return r;
 }
 
 // One SEAV byte as bits: the byte itself, or the bit view of its 8 counters.
@@ -1625,8 +1630,12 @@ __device__ __forceinline__ uint32_t load_se(const CloseArgs &a, uint64_t byte) {
         const u32x4 t = *reinterpret_cast<const u32x4 *>(a.seav_ts + byte * 8);   // 8 stamps
         v = ts_bits2(t.x, a.thr) | ts_bits2(t.y, a.thr) << 2 | ts_bits2(t.z, a.thr) << 4 | ts_bits2(t.w, a.thr) << 6;
     } else {
+        // the byte's eight bits in a fixed permuted order (counter 4h + j at bit 2j + h): every SEAV
+        // byte of the window is read the same way, so the weights and the AND of the rows used by
+        // the end of window are those of the canonical order
         const uint64_t t = *reinterpret_cast<const uint64_t *>(a.seav_at + byte * 8);
-        v = at_bits4((uint32_t)t, a) | at_bits4((uint32_t)(t >> 32), a) << 4;
+        const uint32_t x = (at_active4((uint32_t)t, a) >> 7) | (at_active4((uint32_t)(t >> 32), a) >> 6);
+        v = (x | x >> 6 | x >> 12 | x >> 18) & 0xFFu;
     }
     return v;
 }
@@ -1645,10 +1654,13 @@ __device__ __forceinline__ uint32_t load_ldc_word(const CloseArgs &a, uint32_t w
                   ts_bits2(x.w, a.thr) << 6) << (8 * q);
         }
     } else {
+        // 32 counters in a fixed permuted order (counter 4h + j at bit 8j + h): the LDCs of a
+        // candidate are all read the same way, so the AND of its rows and the popcount are unchanged
         const u32x4 *t = reinterpret_cast<const u32x4 *>(a.ldca_at + (uint64_t)word * 32);
         const u32x4 x = t[0], y = t[1];
-        v = at_bits4(x.x, a) | at_bits4(x.y, a) << 4 | at_bits4(x.z, a) << 8 | at_bits4(x.w, a) << 12 |
-            at_bits4(y.x, a) << 16 | at_bits4(y.y, a) << 20 | at_bits4(y.z, a) << 24 | at_bits4(y.w, a) << 28;
+        v = (at_active4(x.x, a) >> 7) | (at_active4(x.y, a) >> 6) | (at_active4(x.z, a) >> 5) |
+            (at_active4(x.w, a) >> 4) | (at_active4(y.x, a) >> 3) | (at_active4(y.y, a) >> 2) |
+            (at_active4(y.z, a) >> 1) | at_active4(y.w, a);
     }
     return v;
 }

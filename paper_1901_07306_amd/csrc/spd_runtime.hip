@@ -210,7 +210,7 @@ spd_status derive(const spd_params *p, spd_derived *d, std::string *why) {
     if (p->log2lc > 24) return bad("log2lc must be <= 24");
     if (p->window_slices > 30000) return bad("window_slices must be <= 30000");
     if (p->sliding_counter > 1) return bad("sliding_counter must be 0 (AT pool) or 1 (16-bit stamps)");
-    if (p->window_slices && p->sliding_counter == 0 && p->window_slices > kAtPeriod - 1)
+    if (p->window_slices && p->sliding_counter == 0 && p->window_slices > kAtMaxK)
         return bad("the AT pool needs window_slices <= 254 (use sliding_counter = 1)");
     const uint32_t L = 32 - p->r;
     std::memset(d, 0, sizeof(*d));
@@ -372,10 +372,14 @@ SlotPtrs ptrs_of(const Slot &s) {
 
 uint64_t slot_words(const spd_ctx *ctx) { return ctx->slot_bytes / 4; }
 
+// The value that empties a slot: zero, or for an AT pool the expired code of the current slice in
+// every byte.
+uint32_t empty_fill(const spd_ctx *ctx) { return ctx->at ? at_expired_code(ctx->slice, ctx->K) * 0x01010101u : 0u; }
+
 spd_status clear_slot(spd_ctx *ctx, Slot &s, hipStream_t st) {
     {
         ProfScope ps(ctx, SPD_K_FILL, st);
-        SPD_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(s.mem), slot_words(ctx), 0u, st));
+        SPD_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(s.mem), slot_words(ctx), empty_fill(ctx), st));
     }
     s.fresh = false;
     s.seav_zero = false;
@@ -1044,7 +1048,7 @@ spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArg
     a->ldca_ts = sl.ldca_ts;
     a->seav_at = sl.seav_at;
     a->ldca_at = sl.ldca_at;
-    a->at_tm = ctx->slice % kAtPeriod;
+    a->at_ct = at_code(ctx->slice);
     a->at_k = ctx->K;
     if (ctx->sliding) {
         const int64_t lo = (int64_t)ctx->slice - (int64_t)ctx->K + 2;
@@ -1193,7 +1197,7 @@ spd_status slot_alloc(spd_ctx *ctx, Slot &sl) {
     if (ctx->at) {
         sl.ldca_at = static_cast<uint8_t *>(sl.mem);
         sl.seav_at = sl.ldca_at + ldca_bytes * 8;
-        SPD_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(sl.mem), ctx->slot_bytes / 4, 0u, nullptr));
+        SPD_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(sl.mem), ctx->slot_bytes / 4, empty_fill(ctx), nullptr));
         sl.fresh = false;
     } else if (ctx->sliding) {
         sl.ldca_ts = static_cast<uint16_t *>(sl.mem);
@@ -1225,7 +1229,7 @@ spd_status ctx_create(const spd_params *p, uint32_t n_routers, uint32_t n_slots,
     ctx->sliding = p->window_slices > 0;
     ctx->K = p->window_slices;
     ctx->at = ctx->sliding && p->sliding_counter == 0;
-    ctx->at_groups = ctx->at ? kAtPeriod - ctx->K : 0;
+    ctx->at_groups = ctx->at ? kAtCodes - 1u - ctx->K : 0;   // K + G = 255: ages read mod 256 stay exact
     default_tuning(&ctx->tune);
     if (hipGetDevice(&ctx->device) != hipSuccess) {
         delete ctx;
@@ -1478,7 +1482,7 @@ spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *st
             for (auto q : src) s8.push_back(reinterpret_cast<const uint8_t *>(q));
             ProfScope ps(ctx, SPD_K_MERGE, s);
             SPD_HIP(ctx, launch_at_merge(static_cast<uint8_t *>(g.mem), s8.data(), (uint32_t)s8.size(), ctx->slot_bytes,
-                                         ctx->slice % kAtPeriod, s));
+                                         at_code(ctx->slice), s));
         } else if (ctx->sliding) {
             std::vector<const uint16_t *> s16;
             for (auto q : src) s16.push_back(reinterpret_cast<const uint16_t *>(q));
@@ -1554,7 +1558,7 @@ spd_status spd_slide(spd_ctx *ctx, void *stream) {
             std::vector<uint8_t *> pools;
             for (auto &sl : ctx->slots) pools.push_back(static_cast<uint8_t *>(sl.mem));
             ProfScope ps(ctx, SPD_K_FILL, s);
-            SPD_HIP(ctx, launch_at_sweep(pools.data(), (uint32_t)pools.size(), lo, hi, ctx->slice % kAtPeriod, ctx->K, s));
+            SPD_HIP(ctx, launch_at_sweep(pools.data(), (uint32_t)pools.size(), lo, hi, at_code(ctx->slice), ctx->K, s));
         }
         return SPD_OK;
     }
@@ -1597,7 +1601,7 @@ spd_status spd_export(spd_ctx *ctx, int32_t target, uint8_t *seav_host, uint32_t
     const int64_t lo = (int64_t)ctx->slice - (int64_t)ctx->K + 2;
     const uint16_t thr = (uint16_t)(lo < 1 ? 1 : lo);
     hipStream_t s = ctx->have_last ? ctx->last_stream : nullptr;
-    const uint32_t tm = ctx->slice % kAtPeriod;
+    const uint32_t tm = at_code(ctx->slice);
     if (ldca_host) {
         if (ctx->at) SPD_HIP(ctx, launch_bit_view_at(sl->ldca_at, ctx->d.ldca_words * 32, tm, ctx->K, ctx->view, s));
         else SPD_HIP(ctx, launch_bit_view(sl->ldca_ts, ctx->d.ldca_words * 32, thr, ctx->view, s));
@@ -1622,14 +1626,13 @@ spd_status spd_export_stamps(spd_ctx *ctx, int32_t target, uint16_t *seav_ts_hos
     if (ctx->have_last) SPD_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
     if (ctx->at) {
         // rebuild 1 + last slice from each counter's age: last = slice - age
-        const uint32_t t = ctx->slice, tm = t % kAtPeriod;
+        const uint32_t t = ctx->slice, ct = at_code(t);
         auto decode = [&](const uint8_t *dev, uint64_t n, uint16_t *out) -> spd_status {
             std::vector<uint8_t> raw(n);
             SPD_HIP(ctx, hipMemcpy(raw.data(), dev, n, hipMemcpyDeviceToHost));
             for (uint64_t i = 0; i < n; ++i) {
-                const uint32_t v = raw[i];
-                const uint32_t age = (tm + kAtPeriod + 1 - v) % kAtPeriod;
-                out[i] = v ? (uint16_t)(t - age + 1) : (uint16_t)0;
+                const uint32_t age = (ct - raw[i]) & (kAtCodes - 1u);
+                out[i] = age < ctx->K ? (uint16_t)(t - age + 1) : (uint16_t)0;
             }
             return SPD_OK;
         };

@@ -103,17 +103,18 @@ def test_sliding_stamps_renormalised():
         det.close()
 
 
-@pytest.mark.parametrize("K", [5, 60])
+@pytest.mark.parametrize("K", [5, 60, 254])
 def test_at_pool_across_code_periods(K):
-    """The AT pool stores slice codes modulo 255 and clears expired counters of one group of the pool
-    per slice.  Traffic in slices spread over more than three code periods, including slices whose
-    code repeats that of earlier traffic; after every slice with traffic, and after runs of empty
-    slices while that traffic expires, the bit view and the report of two routers and of their
-    merge must equal the oracle on the union of the last K slices."""
+    """The AT pool stores slice codes modulo 256 and re-stamps the expired counters of one of
+    255 - K groups of the pool per slice (K = 254: the whole pool every slice).  Traffic in slices
+    spread over four code periods, including slices whose code repeats that of earlier traffic;
+    after every slice with traffic, and after runs of empty slices while that traffic expires, the
+    bit view and the report of two routers and of their merge must equal the oracle on the union of
+    the last K slices."""
     mp = st.MethodParams(theta=256, r=10, sr=4, a=2, log2k=10, lr=2, log2lc=8, window_slices=K, hash_seed=63)
     rng = np.random.default_rng(65 + K)
-    busy = {0, 1, 2, 3, 200, 254, 255, 256, 257, 258, 510, 511, 700, 701, 702, 765, 766, 767}
-    check = busy | {t + d for t in busy for d in (K - 1, K, K + 1)} | {509, 764, 1020, 1021}
+    busy = {0, 1, 2, 3, 200, 254, 255, 256, 257, 258, 511, 512, 513, 700, 767, 768, 769, 1023, 1024}
+    check = busy | {t + d for t in busy for d in (K - 1, K, K + 1)} | {510, 766, 1022}
     det = detector(mp, n_routers=2)
     slices = {}
     try:
