@@ -301,7 +301,8 @@ def bench_sliding(spd, torch, np, st):
     n, T = xs[0].shape[0], len(xs)
     dl, dms = timed[dom]
     e = {"value": n * T / el, "unit": "packets/s", "ms_per_slice": el / T * 1e3,
-         "roofline": dict(roofline(dom, n, dl, dms), bound="random stores (one 16-bit stamp per bit set)"),
+         "roofline": dict(roofline(dom, n, dl, dms), bound="random stores (one 8-bit AT code per bit set)" if params.sliding_counter == spd.SLIDING_AT
+                                             else "random stores (one 16-bit stamp per bit set)"),
          "kernel_ms_per_slice": {k: v[1] / T for k, v in kinds.items()},
          "reports": T, "mean_reported": float(np.mean([len(r) for r in reps])),
          "workload": "sliding_300x1m: 300 slices x 1,000,000 pairs, window K = 60 slices, 1M Zipf(1.1)<=500 "

@@ -254,7 +254,9 @@ struct CloseArgs {
     uint32_t at_ct;      // sliding, AT pool: code of the current slice
     uint32_t at_k;       // sliding, AT pool: window length K
     uint32_t *rec;       // (ip, z0) pairs
-    uint32_t *counters;  // [0] reported, [1] candidates
+    uint32_t *counters;  // [0] reported, [1] candidates; zero at launch, left zero by k_close_out
+    uint32_t *host_out;  // host-visible: the counters, then the first host_recs records
+    uint32_t host_recs;
     uint32_t rec_cap;
     uint32_t n_rp;
     uint32_t list_stride;

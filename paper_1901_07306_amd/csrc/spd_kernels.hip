@@ -910,6 +910,7 @@ __global__ __launch_bounds__(BLOCK) void k_region(Consts c, BinGeometry g, Batch
     if (tid == 0) misc[0] = 0;
     const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
     const uint64_t last = B.n - 1;
+    const bool full = p0 + (uint64_t)(PPT * BLOCK) <= B.n;
     u32x2 pr[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -918,7 +919,7 @@ __global__ __launch_bounds__(BLOCK) void k_region(Consts c, BinGeometry g, Batch
     }
     __syncthreads();
     uint32_t bits[PPT * LR], rk[(PPT * LR + 1) / 2];
-    if (p0 + (uint64_t)(PPT * BLOCK) <= B.n)
+    if (full)
         bin_hash_pairs<LR, PPT, BLOCK, true>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
     else
         bin_hash_pairs<LR, PPT, BLOCK, false>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
@@ -964,7 +965,7 @@ __global__ __launch_bounds__(BLOCK) void k_region(Consts c, BinGeometry g, Batch
         }
     }
     __syncthreads();
-    if (p0 + (uint64_t)(PPT * BLOCK) <= B.n) {   // every lane's items are valid
+    if (full) {   // every lane's items are valid
 #pragma unroll
         for (int k = 0; k < PPT * LR; ++k)
             stage[cl[bits[k] >> g.S] + ((rk[k / 2] >> (16 * (k & 1))) & 0xFFFFu)] = bits[k];
@@ -1924,6 +1925,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     }
 }
 
+// After k_close (the launch boundary orders every workgroup's records before this): the counts
+// and the first records go to host-visible memory, so that no copy follows, and the counters are
+// zeroed for the next launch.  One workgroup.
+__global__ __launch_bounds__(256) void k_close_out(CloseArgs a) {
+    const uint32_t n = a.counters[0], cand = a.counters[1];
+    const uint32_t m = min(min(n, a.rec_cap), a.host_recs);
+    const uint2 *src = reinterpret_cast<const uint2 *>(a.rec);
+    uint2 *dst = reinterpret_cast<uint2 *>(a.host_out + 4);
+    for (uint32_t i = threadIdx.x; i < m; i += 256) dst[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.host_out[0] = n;
+        a.host_out[1] = cand;
+        a.counters[0] = 0u;
+        a.counters[1] = 0u;
+    }
+}
+
 template <int MODE>
 static uint32_t close_occupancy(uint32_t block, uint32_t lds_bytes) {
     int n = 0;
@@ -1952,10 +1971,13 @@ static hipError_t launch_close_mode(const Consts &c, const CloseArgs &a, uint32_
 
 hipError_t launch_close(const Consts &c, const CloseArgs &a, int mode, uint32_t block, uint32_t grid, hipStream_t s) {
     const uint32_t lds = (block / 64) * (c.sr * a.list_stride + a.qcap + a.stage_words) * 4u;
-    if (mode == kCloseStamps) return launch_close_mode<kCloseStamps>(c, a, block, grid, lds, s);
-    if (mode == kCloseAt) return launch_close_mode<kCloseAt>(c, a, block, grid, lds, s);
-    if (mode == kCloseBits) return launch_close_mode<kCloseBits>(c, a, block, grid, lds, s);
-    return hipErrorInvalidValue;
+    hipError_t e = hipErrorInvalidValue;
+    if (mode == kCloseStamps) e = launch_close_mode<kCloseStamps>(c, a, block, grid, lds, s);
+    else if (mode == kCloseAt) e = launch_close_mode<kCloseAt>(c, a, block, grid, lds, s);
+    else if (mode == kCloseBits) e = launch_close_mode<kCloseBits>(c, a, block, grid, lds, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_close_out, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace spd

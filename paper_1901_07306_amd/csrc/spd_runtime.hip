@@ -42,12 +42,14 @@ constexpr uint32_t kRecChunk = 4096;   // records copied back together with the 
 
 // Device and pinned host buffers of one end-of-window pass.
 struct CloseBuf {
-    // one device buffer: 4 counters ([0] reported, [1] candidates) then the (ip, z0) records, so that
-    // the counters and the first kRecChunk records come back in one copy
+    // one device buffer: 4 counters ([0] reported, [1] candidates; zero between launches) then the
+    // (ip, z0) records.  The end-of-window launch itself copies the counters and the first
+    // kRecChunk records to h_counters.
     uint32_t *counters = nullptr;
     uint32_t *rec = nullptr;          // counters + 4
     uint32_t rec_cap = 0;
-    uint32_t *h_counters = nullptr;   // pinned, same layout, kRecChunk records
+    uint32_t *h_counters = nullptr;   // pinned and mapped, same layout, kRecChunk records
+    uint32_t *d_counters = nullptr;   // h_counters' device address
     uint32_t *h_rec = nullptr;        // pinned, all records when there are more than kRecChunk
     uint32_t h_rec_cap = 0;
     bool empty = false;               // the slot was fresh: nothing was launched
@@ -1011,6 +1013,7 @@ spd_status close_rec_alloc(spd_ctx *ctx, CloseBuf &cb, uint32_t cap) {
     cb.rec_cap = 0;
     spd_status st = dev_alloc(ctx, &cb.counters, 16 + (uint64_t)cap * 8);
     if (st) return st;
+    SPD_HIP(ctx, hipMemset(cb.counters, 0, 16));   // once; each launch leaves them zero
     cb.rec = cb.counters + 4;
     cb.rec_cap = cap;
     return SPD_OK;
@@ -1021,7 +1024,10 @@ spd_status close_buf_init(spd_ctx *ctx, CloseBuf &cb) {
         spd_status st = close_rec_alloc(ctx, cb, kRecInit);
         if (st) return st;
     }
-    if (!cb.h_counters) SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_counters, 16 + (uint64_t)kRecChunk * 8, hipHostMallocDefault));
+    if (!cb.h_counters) {
+        SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_counters, 16 + (uint64_t)kRecChunk * 8, hipHostMallocMapped));
+        SPD_HIP(ctx, hipHostGetDevicePointer((void **)&cb.d_counters, cb.h_counters, 0));
+    }
     return SPD_OK;
 }
 
@@ -1033,6 +1039,7 @@ void close_buf_free(spd_ctx *ctx, CloseBuf &cb) {
     if (cb.h_counters) (void)hipHostFree(cb.h_counters);
     if (cb.h_rec) (void)hipHostFree(cb.h_rec);
     cb.h_counters = nullptr;
+    cb.d_counters = nullptr;
     cb.h_rec = nullptr;
     cb.rec_cap = cb.h_rec_cap = 0;
 }
@@ -1057,6 +1064,8 @@ spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArg
     a->counters = cb.counters;
     a->rec = cb.rec;
     a->rec_cap = cb.rec_cap;
+    a->host_out = cb.d_counters;
+    a->host_recs = std::min(cb.rec_cap, kRecChunk);
     a->n_rp = 1u << ctx->p.r;
     uint32_t max_ibn = 0;
     for (uint32_t i = 0; i < ctx->p.sr; ++i) max_ibn = std::max(max_ibn, ctx->d.ibn[i]);
@@ -1087,20 +1096,16 @@ spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArg
     return SPD_OK;
 }
 
-// The device part of the end of window: clear the counters, run k_close, copy the counters and
-// the first kRecChunk records to pinned host memory.  Asynchronous on s.
+// The device part of the end of window: k_close, then k_close_out, which leaves the counters and
+// the first kRecChunk records in pinned host memory (and the device counters zero).  Asynchronous
+// on s.
 spd_status close_launch_ops(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStream_t s) {
     CloseArgs a;
     uint32_t block, grid;
     spd_status st = close_args(ctx, sl, cb, &a, &block, &grid);
     if (st) return st;
-    SPD_HIP(ctx, launch_fill_u32(cb.counters, 4, 0u, s));
-    {
-        ProfScope ps(ctx, SPD_K_CLOSE, s);
-        SPD_HIP(ctx, launch_close(ctx->c, a, close_mode(ctx), block, grid, s));
-    }
-    SPD_HIP(ctx, hipMemcpyAsync(cb.h_counters, cb.counters, 16 + (uint64_t)std::min(cb.rec_cap, kRecChunk) * 8,
-                                hipMemcpyDeviceToHost, s));
+    ProfScope ps(ctx, SPD_K_CLOSE, s);
+    SPD_HIP(ctx, launch_close(ctx->c, a, close_mode(ctx), block, grid, s));
     return SPD_OK;
 }
 
