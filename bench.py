@@ -91,17 +91,22 @@ def roofline(kind, n_pairs, launches, total_ms, traffic=None):
 
 
 def run_detector(spd, torch, params, x, steps, warmup, tune):
-    """Three passes of `steps` windows each (scan + end of window, the report on the host):
+    """Four passes of `steps` windows each (scan + end of window, the report on the host):
     1. every kernel kind timed with the library's HIP events: the per-kernel breakdown and the
        dominant kernel;
-    2. the timed region: back-to-back windows, only the dominant kernel timed (two events per
-       launch, so the timing hardly disturbs the run);
-    3. untimed, a synchronisation after each scan: the end-of-window latency alone."""
+    2. the timed region: back-to-back windows as a capture loop runs them, each window's close
+       begun (spd_close_begin) before the next window's scan is enqueued and its report collected
+       (spd_close_end) after it, so that the GPU does not wait for the host between windows; only
+       the dominant kernel timed (two events per launch, so the timing hardly disturbs the run);
+    3. the same windows with the blocking close (spd_close_window after each scan);
+    4. untimed, a synchronisation after each scan: the end-of-window latency alone."""
+    import numpy as np
     det = spd.Detector(params)
     set_tuning(det, tune)
     for _ in range(warmup):
         det.scan(0, x)
         det.close_window(0)
+        det.close_end(det.close_begin(0))   # (an empty window: warms up the two-part close)
     torch.cuda.synchronize()
     det.profile_enable(True)
     for _ in range(steps):
@@ -113,14 +118,26 @@ def run_detector(spd, torch, params, x, steps, warmup, tune):
     det.profile_enable(True, kinds=[dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rec = None
+    rec, prev = None, None
     for _ in range(steps):
         det.scan(0, x)
-        rec = det.close_window(0)
+        t = det.close_begin(0)
+        if prev is not None:
+            rec = det.close_end(prev)
+        prev = t
+    rec = det.close_end(prev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timed = det.profile()[dom]
     det.profile_enable(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        det.scan(0, x)
+        brec = det.close_window(0)
+    torch.cuda.synchronize()
+    elapsed_blocking = time.perf_counter() - t0
+    assert np.array_equal(brec, rec), "blocking and two-part closes disagree"
     close_ms, window_ms = [], []
     for _ in range(steps):
         torch.cuda.synchronize()
@@ -134,7 +151,7 @@ def run_detector(spd, torch, params, x, steps, warmup, tune):
         window_ms.append((c1 - s0) * 1e3)
     stats = det.stats
     det.close()
-    return elapsed, close_ms, window_ms, breakdown, (dom, timed), rec, stats
+    return elapsed, close_ms, window_ms, breakdown, (dom, timed), rec, stats, elapsed_blocking
 
 
 def config_entry(n, steps, el, close_ms, window_ms, kinds, dom, dom_launches, dom_ms, traffic=None):
@@ -196,9 +213,10 @@ def bench_plain_1m(spd, torch, np, st, at, steps, warmup):
     probe = spd.Detector(params)
     tuned = at.autotune(probe, x, quick=True)
     probe.close()
-    el, close_ms, window_ms, kinds, (dom, (dl, dms)), rec, _ = run_detector(spd, torch, params, x, steps, warmup, tuned)
+    el, close_ms, window_ms, kinds, (dom, (dl, dms)), rec, _, _ = run_detector(spd, torch, params, x, steps, warmup,
+                                                                               tuned)
     e = config_entry(x.shape[0], steps, el, close_ms, window_ms, kinds, dom, dl, dms)
-    pel, _, _, _, _, prec, _ = run_detector(spd, torch, params, x, steps, warmup, {"direct_max_pairs": 1 << 62})
+    pel, _, _, _, _, prec, _, _ = run_detector(spd, torch, params, x, steps, warmup, {"direct_max_pairs": 1 << 62})
     assert np.array_equal(prec, rec), "plain_1m: plain and tuned scans disagree"
     e["plain"] = {"value": x.shape[0] * steps / pel, "unit": "packets/s", "ms_per_step": pel / steps * 1e3}
     e["batched_over_plain"] = e["value"] / e["plain"]["value"]
@@ -583,7 +601,7 @@ def main() -> int:
 
     # the library's binned scan with the tuned settings -- the headline value
     log(f"timing the scan: {args.warmup} warmup + {args.steps} steps")
-    el, close_ms, window_ms, kinds, (dom, (dom_launches, dom_ms)), rec, stats = run_detector(
+    el, close_ms, window_ms, kinds, (dom, (dom_launches, dom_ms)), rec, stats, el_blocking = run_detector(
         spd, torch, params, x, args.steps, args.warmup, tuned)
     if dom_launches != args.steps:
         raise RuntimeError(f"unexpected dominant kernel {dom} ({dom_launches} launches)")
@@ -595,8 +613,8 @@ def main() -> int:
 
     # the plain per-batch kernel: one thread per pair, global atomicOr into the sketches
     log(f"timing plain scan: 1 warmup + {args.plain_steps} steps")
-    pel, pclose, pwin, _, _, prec, _ = run_detector(spd, torch, params, x, args.plain_steps, 1,
-                                                    {"direct_max_pairs": 1 << 62})
+    pel, pclose, pwin, _, _, prec, _, _ = run_detector(spd, torch, params, x, args.plain_steps, 1,
+                                                       {"direct_max_pairs": 1 << 62})
     plain_value = n * args.plain_steps / pel
     assert np.array_equal(prec, rec), "plain and binned scans disagree"
 
@@ -618,7 +636,8 @@ def main() -> int:
                         "sources, 500 planted super points |OP| in [1024,20000], 30% duplicates, theta 1024",
             "method": {"r": w.params.r, "sr": w.params.sr, "a": w.params.a, "log2k": w.params.log2k,
                        "lr": w.params.lr, "log2lc": w.params.log2lc, "theta": w.params.theta},
-            "step": "scan 64Mi pairs (binned LDS scan) + end of window (rebuild, filter, report, reset)",
+            "step": "scan 64Mi pairs (binned LDS scan) + end of window (rebuild, filter, report, reset); "
+                    "windows back to back, each report collected after the next window's scan is enqueued",
             "parallelism": "1 GPU",
         },
         "roofline": head["roofline"],
@@ -629,6 +648,10 @@ def main() -> int:
         "window_latency_ms": head["window_latency_ms"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
         "reported_super_points": int(len(rec)),
+        "blocking_close": {"value": n * args.steps / el_blocking, "unit": "packets/s",
+                           "ms_per_step": el_blocking / args.steps * 1e3,
+                           "step": "scan, then spd_close_window (the host waits for each report before "
+                                   "the next scan is enqueued)"},
         "tuning": {"autotuned": not args.no_autotune, "settings": tuned,
                    "candidates_ms": [[c, ms] for c, ms in tables["binned"]] if tuned else None},
         "plain": {

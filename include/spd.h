@@ -218,6 +218,20 @@ spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *st
 spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_host, uint32_t cap,
                             uint32_t *n_out, void *stream);
 
+/* The end of window in two halves, so that the next window's scans can be enqueued before the
+ * report is collected (Sections 3.3, 4.2).  spd_close_begin enqueues on `stream` the device work of
+ * spd_close_window for the target and, in discrete mode, resets the target at once (the next
+ * scans start a new window); *ticket names the close.  spd_close_end waits for that close and
+ * writes its report as spd_close_window does.  At most SPD_MAX_PENDING_CLOSES closes per context
+ * are pending (begun, not ended; SPD_E_STATE beyond that); they are ended in any order, each once.
+ * A pending close holds room for 65536 super points: if its window has more, spd_close_end returns
+ * SPD_E_TRUNCATED with *n_out = their number and no report (spd_close_window re-runs instead),
+ * and later closes get room for them.  The first spd_close_begin of a context allocates the
+ * buffers of all pending closes (which synchronises the device). */
+#define SPD_MAX_PENDING_CLOSES 4
+spd_status spd_close_begin(spd_ctx *ctx, int32_t target, void *stream, uint32_t *ticket);
+spd_status spd_close_end(spd_ctx *ctx, uint32_t ticket, spd_superpoint *out_host, uint32_t cap, uint32_t *n_out);
+
 /* Start a new window for a target without reporting the current one: the re-initialisation of a
  * watch point's sketch at the start of each window (Sections 3.3, 4.2), e.g. once its sketch has
  * been merged into the global one.  Discrete mode: the slot is marked empty and its next scan

@@ -12,6 +12,7 @@ falling back to anything else.
 from __future__ import annotations
 
 import ctypes
+import threading
 import os
 from typing import Iterable, List, Optional, Sequence, Tuple
 
@@ -90,7 +91,7 @@ class SpdServerStats(ctypes.Structure):
 RECORD = np.dtype([("ip", "<u4"), ("z0", "<u4"), ("est", "<u4"), ("flags", "<u4")])
 
 EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_noalloc", "spd_scan_host", "spd_scan_batches", "spd_merge",
-            "spd_close_window", "spd_reset", "spd_slide", "spd_export", "spd_import", "spd_export_stamps",
+            "spd_close_window", "spd_close_begin", "spd_close_end", "spd_reset", "spd_slide", "spd_export", "spd_import", "spd_export_stamps",
             "spd_current_slice", "spd_get_tuning", "spd_set_tuning", "spd_get_stats", "spd_strerror",
             "spd_last_error", "spd_profile_enable", "spd_profile_select", "spd_get_profile", "spd_server_create", "spd_server_submit",
             "spd_server_next", "spd_server_drain", "spd_server_get_stats", "spd_server_set_tuning",
@@ -149,6 +150,8 @@ def lib(require_torch: bool = True) -> ctypes.CDLL:
         "spd_scan_batches": (i32, [vp, P(SpdBatch), u32, vp]),
         "spd_merge": (i32, [vp, P(u32), u32, vp]),
         "spd_close_window": (i32, [vp, i32, P(SpdSuperpoint), u32, P(u32), vp]),
+        "spd_close_begin": (i32, [vp, i32, vp, P(u32)]),
+        "spd_close_end": (i32, [vp, u32, P(SpdSuperpoint), u32, P(u32)]),
         "spd_slide": (i32, [vp, vp]),
         "spd_reset": (i32, [vp, i32, vp]),
         "spd_export": (i32, [vp, i32, vp, vp]),
@@ -301,17 +304,49 @@ def spd_merge(ctx: int, routers: Sequence[int], stream=None) -> None:
     _check(lib().spd_merge(ctx, arr, len(routers), _stream_ptr(stream)), ctx)
 
 
+_out_bufs = threading.local()   # per thread: the last record buffer handed to spd_close_window
+
+
+def _out_buffer(cap: int):
+    """A reusable ctypes array of cap records (the result is copied out before the next call)."""
+    cap = max(1, cap)
+    b = getattr(_out_bufs, "buf", None)
+    if b is None or len(b) != cap:
+        b = (SpdSuperpoint * cap)()
+        _out_bufs.buf = b
+    return b
+
+
 def spd_close_window(ctx: int, target: int, cap: int = 1 << 16, stream=None) -> np.ndarray:
     """Super points of the target, sorted by ip, as a structured array (ip, z0, est, flags)."""
-    while True:
-        out = (SpdSuperpoint * max(1, cap))()
-        n = u32(0)
-        st = lib().spd_close_window(ctx, target, out, cap, ctypes.byref(n), _stream_ptr(stream))
-        if st == SPD_E_TRUNCATED:
-            raise SpdError(st, f"{n.value} super points exceed cap {cap}")
-        _check(st, ctx)
-        buf = np.frombuffer(out, dtype=RECORD, count=max(1, cap))
-        return buf[: n.value].copy()
+    out = _out_buffer(cap)
+    n = u32(0)
+    st = lib().spd_close_window(ctx, target, out, cap, ctypes.byref(n), _stream_ptr(stream))
+    if st == SPD_E_TRUNCATED:
+        raise SpdError(st, f"{n.value} super points exceed cap {cap}")
+    _check(st, ctx)
+    return np.frombuffer(out, dtype=RECORD, count=len(out))[: n.value].copy()
+
+
+MAX_PENDING_CLOSES = 4   # SPD_MAX_PENDING_CLOSES
+
+
+def spd_close_begin(ctx: int, target: int, stream=None) -> int:
+    """Enqueue the end of window of the target; returns the ticket that spd_close_end collects."""
+    t = u32(0)
+    _check(lib().spd_close_begin(ctx, target, _stream_ptr(stream), ctypes.byref(t)), ctx)
+    return t.value
+
+
+def spd_close_end(ctx: int, ticket: int, cap: int = 1 << 16) -> np.ndarray:
+    """The report of a begun close (waits for it), as spd_close_window returns it."""
+    out = _out_buffer(cap)
+    n = u32(0)
+    st = lib().spd_close_end(ctx, ticket, out, cap, ctypes.byref(n))
+    if st == SPD_E_TRUNCATED:
+        raise SpdError(st, f"{n.value} super points: {lib().spd_last_error(ctx).decode()}")
+    _check(st, ctx)
+    return np.frombuffer(out, dtype=RECORD, count=len(out))[: n.value].copy()
 
 
 def spd_reset(ctx: int, target: int, stream=None) -> None:
@@ -422,6 +457,12 @@ class Detector:
     def close_window(self, target=0, cap=1 << 16, stream=None):
         return spd_close_window(self.ctx, target, cap, stream)
 
+    def close_begin(self, target=0, stream=None) -> int:
+        return spd_close_begin(self.ctx, target, stream)
+
+    def close_end(self, ticket: int, cap=1 << 16):
+        return spd_close_end(self.ctx, ticket, cap)
+
     def reset(self, target=0, stream=None):
         spd_reset(self.ctx, target, stream)
 
@@ -491,12 +532,12 @@ class Server:
     def next(self, timeout_ms: int = -1, cap: int = 1 << 16):
         """(header dict, structured array of super points) or None on timeout."""
         hdr = SpdWindowResult()
-        out = (SpdSuperpoint * max(1, cap))()
+        out = _out_buffer(cap)
         st = lib().spd_server_next(self.h, ctypes.byref(hdr), out, cap, timeout_ms)
         if st == SPD_E_AGAIN:
             return None
         self._check(st)
-        sp = np.frombuffer(out, dtype=RECORD, count=max(1, cap))[: hdr.n_super].copy()
+        sp = np.frombuffer(out, dtype=RECORD, count=len(out))[: hdr.n_super].copy()
         return dict(router=hdr.router, window=hdr.window, pairs=hdr.pairs, latency_ms=hdr.latency_ms,
                     n_super=hdr.n_super), sp
 

@@ -62,6 +62,15 @@ struct CloseBuf {
 
 constexpr uint32_t kBdRing = 4;   // staging slots for the batch descriptors of binned launches
 
+// A close begun with spd_close_begin and not yet collected: its buffers, and an event recorded
+// after its device work.
+struct PendingClose {
+    CloseBuf cb;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    uint32_t seq = 0;   // ticket = seq << 4 | index
+};
+
 struct spd_ctx {
     spd_params p{};
     spd_derived d{};
@@ -101,6 +110,9 @@ struct spd_ctx {
     uint32_t close_per_cu[3] = {0, 0, 0};   // resident end-of-window workgroups per CU (64, 128, 256 lanes)
     uint32_t spill_parity = 0;       // region layout: which of two spill counts the next launch uses
     CloseBuf cbuf;                  // end-of-window buffers of spd_close_window
+    PendingClose pend[SPD_MAX_PENDING_CLOSES];   // spd_close_begin / spd_close_end
+    uint32_t pend_seq = 0;
+    hipStream_t copy_s = nullptr;   // non-blocking: record copies of spd_close_end
     uint32_t *view = nullptr;       // sliding export: bit view words
     uint64_t view_words = 0;
     std::vector<uint32_t> est;      // Eq. 4 estimate for every z0 in [0, k]
@@ -1149,27 +1161,10 @@ spd_status close_launch_graph(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStr
     return SPD_OK;
 }
 
-// Host part, after the launched work has completed: fetch records beyond the first chunk, grow
-// the record buffer and run again if it overflowed (the pass is deterministic), build the sorted
-// report with Eq. 4 estimates.  Discrete mode: the slot becomes fresh (next window from zero).
-spd_status close_finish(spd_ctx *ctx, Slot &sl, CloseBuf &cb, hipStream_t s, std::vector<spd_superpoint> *out) {
-    out->clear();
-    ctx->stats.closes++;
-    if (cb.empty) {
-        ctx->stats.candidates_last = 0;
-        ctx->stats.reported_last = 0;
-        return SPD_OK;
-    }
-    uint32_t n = cb.h_counters[0];
+// The report of a finished close whose first n records (n <= rec_cap) are in cb: fetch those past
+// the first chunk (a copy on s), Eq. 4 estimates, sorted by ip.
+spd_status close_report(spd_ctx *ctx, CloseBuf &cb, uint32_t n, hipStream_t s, std::vector<spd_superpoint> *out) {
     ctx->stats.candidates_last = cb.h_counters[1];
-    if (n > cb.rec_cap) {
-        spd_status st = close_rec_alloc(ctx, cb, n + 1024);
-        if (st) return st;
-        st = close_launch_ops(ctx, sl, cb, s);
-        if (st) return st;
-        SPD_HIP(ctx, hipStreamSynchronize(s));
-        n = cb.h_counters[0];
-    }
     if (n > kRecChunk) {
         if (n > cb.h_rec_cap) {
             (void)hipHostFree(cb.h_rec);
@@ -1190,6 +1185,31 @@ spd_status close_finish(spd_ctx *ctx, Slot &sl, CloseBuf &cb, hipStream_t s, std
     }
     std::sort(out->begin(), out->end(), [](const spd_superpoint &x, const spd_superpoint &y) { return x.ip < y.ip; });
     ctx->stats.reported_last = n;
+    return SPD_OK;
+}
+
+// Host part, after the launched work has completed: fetch records beyond the first chunk, grow
+// the record buffer and run again if it overflowed (the pass is deterministic), build the sorted
+// report with Eq. 4 estimates.  Discrete mode: the slot becomes fresh (next window from zero).
+spd_status close_finish(spd_ctx *ctx, Slot &sl, CloseBuf &cb, hipStream_t s, std::vector<spd_superpoint> *out) {
+    out->clear();
+    ctx->stats.closes++;
+    if (cb.empty) {
+        ctx->stats.candidates_last = 0;
+        ctx->stats.reported_last = 0;
+        return SPD_OK;
+    }
+    uint32_t n = cb.h_counters[0];
+    if (n > cb.rec_cap) {
+        spd_status st = close_rec_alloc(ctx, cb, n + 1024);
+        if (st) return st;
+        st = close_launch_ops(ctx, sl, cb, s);
+        if (st) return st;
+        SPD_HIP(ctx, hipStreamSynchronize(s));
+        n = cb.h_counters[0];
+    }
+    spd_status st = close_report(ctx, cb, n, s, out);
+    if (st) return st;
     if (!ctx->sliding) sl.fresh = true;   // the next window starts from zero
     return SPD_OK;
 }
@@ -1355,6 +1375,11 @@ void spd_destroy(spd_ctx *ctx) {
         }
         if (ctx->h2d_s) (void)hipStreamDestroy(ctx->h2d_s);
         close_buf_free(ctx, ctx->cbuf);
+        for (auto &pc : ctx->pend) {
+            close_buf_free(ctx, pc.cb);
+            if (pc.done) (void)hipEventDestroy(pc.done);
+        }
+        if (ctx->copy_s) (void)hipStreamDestroy(ctx->copy_s);
         dev_free(ctx, &ctx->view, ctx->view_words * 4);
         if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
         prof_harvest(ctx);
@@ -1525,6 +1550,82 @@ spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_ho
         ProfScope ps(ctx, SPD_K_FILL, s);
         SPD_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sl->seav), ctx->seav_alloc / 4, 0u, s));
         sl->seav_zero = true;
+    }
+    const uint32_t n = (uint32_t)res.size();
+    const uint32_t w = std::min(n, cap);
+    if (w) std::memcpy(out_host, res.data(), (size_t)w * sizeof(spd_superpoint));
+    *n_out = n;
+    return n > cap ? fail(ctx, SPD_E_TRUNCATED, "output capacity smaller than the number of super points") : SPD_OK;
+}
+
+spd_status spd_close_begin(spd_ctx *ctx, int32_t target, void *stream, uint32_t *ticket) {
+    if (!ctx) return SPD_E_INVALID;
+    if (!ticket) return fail(ctx, SPD_E_INVALID, "null ticket");
+    Slot *sl = slot_of(ctx, target);
+    if (!sl) return fail(ctx, SPD_E_STATE, "bad target");
+    uint32_t i = 0;
+    while (i < SPD_MAX_PENDING_CLOSES && ctx->pend[i].busy) ++i;
+    if (i == SPD_MAX_PENDING_CLOSES) return fail(ctx, SPD_E_STATE, "too many closes pending: collect one first");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!ctx->copy_s) {
+        // the first two-part close allocates the buffers of every pending close (allocation
+        // synchronises the device: not in the middle of a pipeline)
+        for (auto &q : ctx->pend) {
+            spd_status st = close_buf_init(ctx, q.cb);
+            if (st) return st;
+            if (!q.done) SPD_HIP(ctx, hipEventCreateWithFlags(&q.done, hipEventDisableTiming));
+        }
+        SPD_HIP(ctx, hipStreamCreateWithFlags(&ctx->copy_s, hipStreamNonBlocking));
+    }
+    PendingClose &pc = ctx->pend[i];
+    order_stream(ctx, s);
+    spd_status st = close_launch(ctx, *sl, pc.cb, s);
+    if (st) return st;
+    if (!ctx->sliding) {
+        if (!pc.cb.empty) {
+            // the next window's scans, enqueued after this, start from a zero SEAV
+            ProfScope ps(ctx, SPD_K_FILL, s);
+            SPD_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sl->seav), ctx->seav_alloc / 4, 0u, s));
+            sl->seav_zero = true;
+        }
+        sl->fresh = true;
+    }
+    SPD_HIP(ctx, hipEventRecord(pc.done, s));
+    pc.busy = true;
+    pc.seq = (++ctx->pend_seq) & 0x0FFFFFFFu;
+    *ticket = (pc.seq << 4) | i;
+    return SPD_OK;
+}
+
+spd_status spd_close_end(spd_ctx *ctx, uint32_t ticket, spd_superpoint *out_host, uint32_t cap, uint32_t *n_out) {
+    if (!ctx) return SPD_E_INVALID;
+    if (!n_out || (cap && !out_host)) return fail(ctx, SPD_E_INVALID, "null output");
+    *n_out = 0;
+    const uint32_t i = ticket & 15u;
+    if (i >= SPD_MAX_PENDING_CLOSES || !ctx->pend[i].busy || ctx->pend[i].seq != (ticket >> 4))
+        return fail(ctx, SPD_E_STATE, "unknown or already collected close ticket");
+    DeviceGuard dg(ctx->device);
+    PendingClose &pc = ctx->pend[i];
+    pc.busy = false;   // the ticket is spent whatever follows
+    SPD_HIP(ctx, hipEventSynchronize(pc.done));
+    ctx->stats.closes++;
+    std::vector<spd_superpoint> res;
+    if (pc.cb.empty) {
+        ctx->stats.candidates_last = 0;
+        ctx->stats.reported_last = 0;
+    } else {
+        const uint32_t n = pc.cb.h_counters[0];
+        if (n > pc.cb.rec_cap) {
+            // the window's sketch may be rewritten already, so there is no re-run: the report is
+            // lost, and later closes get a buffer large enough for it
+            spd_status st = close_rec_alloc(ctx, pc.cb, n + 1024);
+            if (st) return st;
+            *n_out = n;
+            return fail(ctx, SPD_E_TRUNCATED, "more super points than the close's record buffer held");
+        }
+        spd_status st = close_report(ctx, pc.cb, n, ctx->copy_s, &res);
+        if (st) return st;
     }
     const uint32_t n = (uint32_t)res.size();
     const uint32_t w = std::min(n, cap);
