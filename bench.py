@@ -296,16 +296,23 @@ def bench_sliding(spd, torch, np, st):
     params = spd.params_from(w.params)
 
     def run(kinds_mask):
+        # each slice's report is collected after the next slice is enqueued (the two-part close)
         det = spd.Detector(params)
+        det.close_end(det.close_begin(0))   # allocates the two-part close's buffers
         det.profile_enable(True, kinds=kinds_mask)
         reps = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        prev = None
         for t, x in enumerate(xs):
             if t:
                 det.slide()
             det.scan(0, x)
-            reps.append(det.close_window(0))
+            tk = det.close_begin(0)
+            if prev is not None:
+                reps.append(det.close_end(prev))
+            prev = tk
+        reps.append(det.close_end(prev))
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         prof = {k: v for k, v in det.profile().items() if v[0]}
@@ -325,7 +332,8 @@ def bench_sliding(spd, torch, np, st):
          "reports": T, "mean_reported": float(np.mean([len(r) for r in reps])),
          "workload": "sliding_300x1m: 300 slices x 1,000,000 pairs, window K = 60 slices, 1M Zipf(1.1)<=500 "
                      "sources, 200 planted with onset/offset; one report per slice",
-         "step": "slide + scan of one slice + report of the window ending at it"}
+         "step": "slide + scan of one slice + report of the window ending at it (collected after the next "
+                 "slice is enqueued)"}
     del xs
     return e, slices, reps
 

@@ -1641,29 +1641,48 @@ __device__ __forceinline__ uint32_t load_se(const CloseArgs &a, uint64_t byte) {
     return v;
 }
 
-// One LDCA word as bits (word < 2^27: a sketch has fewer than 2^32 bits).
+// The counters behind one LDCA word (word < 2^27: a sketch has fewer than 2^32 bits), as loaded:
+// 32 16-bit stamps (four 16-byte vectors) or 32 AT counters (two).
 template <int MODE>
-__device__ __forceinline__ uint32_t load_ldc_word(const CloseArgs &a, uint32_t word) {
-    if (MODE == kCloseBits) return a.ldca[word];
+struct LdcRaw {
+    u32x4 v[MODE == kCloseStamps ? 4 : 2];
+};
+template <int MODE>
+__device__ __forceinline__ LdcRaw<MODE> load_ldc_raw(const CloseArgs &a, uint32_t word) {
+    LdcRaw<MODE> r;
+    const u32x4 *t = MODE == kCloseStamps ? reinterpret_cast<const u32x4 *>(a.ldca_ts + (uint64_t)word * 32)
+                                          : reinterpret_cast<const u32x4 *>(a.ldca_at + (uint64_t)word * 32);
+#pragma unroll
+    for (uint32_t q = 0; q < (MODE == kCloseStamps ? 4u : 2u); ++q) r.v[q] = t[q];
+    return r;
+}
+// Their bit view.
+template <int MODE>
+__device__ __forceinline__ uint32_t decode_ldc(const CloseArgs &a, const LdcRaw<MODE> &r) {
     uint32_t v = 0;
     if (MODE == kCloseStamps) {
-        const u32x4 *t = reinterpret_cast<const u32x4 *>(a.ldca_ts + (uint64_t)word * 32);   // 32 stamps
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
-            const u32x4 x = t[q];
+            const u32x4 x = r.v[q];
             v |= (ts_bits2(x.x, a.thr) | ts_bits2(x.y, a.thr) << 2 | ts_bits2(x.z, a.thr) << 4 |
                   ts_bits2(x.w, a.thr) << 6) << (8 * q);
         }
     } else {
         // 32 counters in a fixed permuted order (counter 4h + j at bit 8j + h): the LDCs of a
         // candidate are all read the same way, so the AND of its rows and the popcount are unchanged
-        const u32x4 *t = reinterpret_cast<const u32x4 *>(a.ldca_at + (uint64_t)word * 32);
-        const u32x4 x = t[0], y = t[1];
+        const u32x4 x = r.v[0], y = r.v[1];
         v = (at_active4(x.x, a) >> 7) | (at_active4(x.y, a) >> 6) | (at_active4(x.z, a) >> 5) |
             (at_active4(x.w, a) >> 4) | (at_active4(y.x, a) >> 3) | (at_active4(y.y, a) >> 2) |
             (at_active4(y.z, a) >> 1) | at_active4(y.w, a);
     }
     return v;
+}
+
+// One LDCA word as bits.
+template <int MODE>
+__device__ __forceinline__ uint32_t load_ldc_word(const CloseArgs &a, uint32_t word) {
+    if (MODE == kCloseBits) return a.ldca[word];
+    return decode_ldc<MODE>(a, load_ldc_raw<MODE>(a, word));
 }
 
 // Orders LDS traffic between lanes of one wavefront (writes by some lanes, reads by others).
@@ -1691,15 +1710,30 @@ __device__ void filter_queue_counters(const CloseArgs &a, const Consts &c, const
         const uint32_t h = queue[e];
         uint32_t ones = 0;
         for (uint32_t w0 = 0; w0 < words; w0 += 128) {
-            const uint32_t wa = w0 + lane, wb = w0 + 64 + lane;
+            const uint32_t wa = w0 + lane < words ? w0 + lane : words - 1;
+            const uint32_t wb = w0 + 64 + lane < words ? w0 + 64 + lane : words - 1;
             uint32_t ua = 0xFFFFFFFFu, ub = 0xFFFFFFFFu;
-            // a runtime loop over the rows keeps the decoding code small (instruction cache)
-            for (uint32_t r = 0; r < c.lr; ++r) {
-                const uint32_t base = ((r << c.log2lc) | ldc_col(h, r, c)) << (c.log2k - 5);
-                ua &= load_ldc_word<MODE>(a, base + (wa < words ? wa : words - 1));
-                ub &= load_ldc_word<MODE>(a, base + (wb < words ? wb : words - 1));
+            // a runtime loop over the rows keeps the decoding code small (instruction cache); AT
+            // counters of two rows at a time are loaded before either is decoded (one round trip
+            // per two rows; the larger 16-bit stamps go one row at a time)
+            if constexpr (MODE == kCloseAt) {
+                for (uint32_t r = 0; r < c.lr; r += 2) {
+                    const uint32_t r1 = r + 1 < c.lr ? r + 1 : r;
+                    const uint32_t b0 = ((r << c.log2lc) | ldc_col(h, r, c)) << (c.log2k - 5);
+                    const uint32_t b1 = ((r1 << c.log2lc) | ldc_col(h, r1, c)) << (c.log2k - 5);
+                    const LdcRaw<MODE> x0 = load_ldc_raw<MODE>(a, b0 + wa), y0 = load_ldc_raw<MODE>(a, b0 + wb);
+                    const LdcRaw<MODE> x1 = load_ldc_raw<MODE>(a, b1 + wa), y1 = load_ldc_raw<MODE>(a, b1 + wb);
+                    ua &= decode_ldc<MODE>(a, x0) & decode_ldc<MODE>(a, x1);
+                    ub &= decode_ldc<MODE>(a, y0) & decode_ldc<MODE>(a, y1);
+                }
+            } else {
+                for (uint32_t r = 0; r < c.lr; ++r) {
+                    const uint32_t b0 = ((r << c.log2lc) | ldc_col(h, r, c)) << (c.log2k - 5);
+                    ua &= load_ldc_word<MODE>(a, b0 + wa);
+                    ub &= load_ldc_word<MODE>(a, b0 + wb);
+                }
             }
-            ones += (wa < words ? __popc(ua) : 0u) + (wb < words ? __popc(ub) : 0u);
+            ones += (w0 + lane < words ? __popc(ua) : 0u) + (w0 + 64 + lane < words ? __popc(ub) : 0u);
         }
         ones = wave_sum(ones);
         const uint32_t z0 = (1u << c.log2k) - ones;
