@@ -295,12 +295,12 @@ def bench_sliding(spd, torch, np, st):
     xs = [torch.from_numpy(p.view(np.int32)).to("cuda") for p in slices]
     params = spd.params_from(w.params)
 
-    def run(kinds_mask):
+    def run(kinds_mask, count=False):
         # each slice's report is collected after the next slice is enqueued (the two-part close)
         det = spd.Detector(params)
         det.close_end(det.close_begin(0))   # allocates the two-part close's buffers
         det.profile_enable(True, kinds=kinds_mask)
-        reps = []
+        reps, cands = [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         prev = None
@@ -311,18 +311,22 @@ def bench_sliding(spd, torch, np, st):
             tk = det.close_begin(0)
             if prev is not None:
                 reps.append(det.close_end(prev))
+                if count:
+                    cands.append(det.stats.candidates_last)
             prev = tk
         reps.append(det.close_end(prev))
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        if count:
+            cands.append(det.stats.candidates_last)
         prof = {k: v for k, v in det.profile().items() if v[0]}
         det.close()
-        return el, prof, reps
+        return el, prof, reps, cands
 
-    _, kinds, _ = run(None)
+    _, kinds, _, cands = run(None, count=True)
     scan_only = {k: v for k, v in kinds.items() if k in SCAN_KINDS}
     dom = max(scan_only, key=lambda k: scan_only[k][1])
-    el, timed, reps = run([dom])
+    el, timed, reps, _ = run([dom])
     n, T = xs[0].shape[0], len(xs)
     dl, dms = timed[dom]
     e = {"value": n * T / el, "unit": "packets/s", "ms_per_slice": el / T * 1e3,
@@ -330,6 +334,7 @@ def bench_sliding(spd, torch, np, st):
                                              else "random stores (one 16-bit stamp per bit set)"),
          "kernel_ms_per_slice": {k: v[1] / T for k, v in kinds.items()},
          "reports": T, "mean_reported": float(np.mean([len(r) for r in reps])),
+         "mean_candidates": float(np.mean(cands)),
          "workload": "sliding_300x1m: 300 slices x 1,000,000 pairs, window K = 60 slices, 1M Zipf(1.1)<=500 "
                      "sources, 200 planted with onset/offset; one report per slice",
          "step": "slide + scan of one slice + report of the window ending at it (collected after the next "
@@ -656,6 +661,7 @@ def main() -> int:
         "window_latency_ms": head["window_latency_ms"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
         "reported_super_points": int(len(rec)),
+        "candidates": int(stats.candidates_last),
         "blocking_close": {"value": n * args.steps / el_blocking, "unit": "packets/s",
                            "ms_per_step": el_blocking / args.steps * 1e3,
                            "step": "scan, then spd_close_window (the host waits for each report before "
