@@ -112,6 +112,7 @@ struct spd_ctx {
     CloseBuf cbuf;                  // end-of-window buffers of spd_close_window
     PendingClose pend[SPD_MAX_PENDING_CLOSES];   // spd_close_begin / spd_close_end
     uint32_t pend_seq = 0;
+    uint32_t pend_rec = 0;          // record room a pending close must have (grown after an overflow)
     hipStream_t copy_s = nullptr;   // non-blocking: record copies of spd_close_end
     uint32_t *view = nullptr;       // sliding export: bit view words
     uint64_t view_words = 0;
@@ -1579,6 +1580,10 @@ spd_status spd_close_begin(spd_ctx *ctx, int32_t target, void *stream, uint32_t 
         SPD_HIP(ctx, hipStreamCreateWithFlags(&ctx->copy_s, hipStreamNonBlocking));
     }
     PendingClose &pc = ctx->pend[i];
+    if (pc.cb.rec_cap < ctx->pend_rec) {
+        spd_status st = close_rec_alloc(ctx, pc.cb, ctx->pend_rec);   // (idle: its last close has ended)
+        if (st) return st;
+    }
     order_stream(ctx, s);
     spd_status st = close_launch(ctx, *sl, pc.cb, s);
     if (st) return st;
@@ -1619,8 +1624,7 @@ spd_status spd_close_end(spd_ctx *ctx, uint32_t ticket, spd_superpoint *out_host
         if (n > pc.cb.rec_cap) {
             // the window's sketch may be rewritten already, so there is no re-run: the report is
             // lost, and later closes get a buffer large enough for it
-            spd_status st = close_rec_alloc(ctx, pc.cb, n + 1024);
-            if (st) return st;
+            ctx->pend_rec = std::max(ctx->pend_rec, n + 1024);
             *n_out = n;
             return fail(ctx, SPD_E_TRUNCATED, "more super points than the close's record buffer held");
         }

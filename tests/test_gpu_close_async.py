@@ -117,3 +117,33 @@ def test_global_empty_and_sliding_match_blocking_close():
                 assert_same_report(blocking, want, f"slice {t}, blocking")
         finally:
             det.close()
+
+
+def test_pending_close_record_overflow_then_room():
+    """A window with more super points than a pending close's record room (65536): spd_close_end
+    reports SPD_E_TRUNCATED with their number (the window may already be rewritten, so nothing is
+    re-run); every later close has room, and the same window scanned again is reported in full."""
+    mp = st.MethodParams(theta=8, r=16, sr=4, a=2, log2k=6, lr=2, log2lc=16, hash_seed=41)
+    rng = np.random.default_rng(43)
+    pairs, _ = heavy_hosts(rng, 90_000, 24)
+    want = oracle_sketch(mp, pairs).detect()
+    assert len(want) > 65536
+    det = spd.Detector(spd.params_from(mp))
+    set_tuning(det, direct_max_pairs=0)
+    try:
+        log("case pending close past its record room")
+        x = to_dev(pairs)
+        det.scan(0, x)
+        with pytest.raises(spd.SpdError) as e:
+            det.close_end(det.close_begin(0), cap=200_000)
+        assert e.value.status == spd.SPD_E_TRUNCATED
+        assert str(len(want)) in str(e.value)
+        # every pending slot (all in use at once) now has room
+        tickets = []
+        for _ in range(spd.MAX_PENDING_CLOSES):
+            det.scan(0, x)
+            tickets.append(det.close_begin(0))
+        for k, t in enumerate(tickets):
+            assert_same_report(det.close_end(t, cap=200_000), want, f"again {k}")
+    finally:
+        det.close()
