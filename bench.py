@@ -343,7 +343,8 @@ def bench_sliding(spd, torch, np, st):
     return e, slices, reps
 
 
-def bench_serving(spd, torch, np, st, capacity_pps, windows_per_router, loads, tuned, budget, max_slots):
+def bench_serving(spd, torch, np, st, capacity_pps, windows_per_router, loads, tuned, budget, max_slots,
+                  min_scan_pairs=0, use_graphs=True):
     """The serving loop on the 16-router workload: batches of log-uniform size in [4Ki, 4Mi] pairs,
     Poisson arrivals at load x capacity_pps, a window closed every 64Mi pairs per router.  Router
     r's window w replays pool window (r + w) mod 4 of plain_64m-shaped traffic (1000 planted super
@@ -390,10 +391,11 @@ def bench_serving(spd, torch, np, st, capacity_pps, windows_per_router, loads, t
             tensors.append(per_router[r][cursor[r]])
             cursor[r] += 1
         srv = spd.Server(params, n_routers=R, window_pairs=W, hbm_budget_bytes=budget, max_slots=max_slots,
-                         max_group_pairs=64 << 20, use_graphs=True, tuning=t)
+                         max_group_pairs=64 << 20, use_graphs=use_graphs, tuning=t, min_scan_pairs=min_scan_pairs)
+        sched = srv.schedule(times, routers, tensors)   # the arrival array, built before the clock starts
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        srv.replay(times, routers, tensors)
+        srv.replay(sched)
         lat, rep = [], {}
         for _ in range(R * windows_per_router):
             got = srv.next(timeout_ms=120000)

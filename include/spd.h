@@ -306,7 +306,9 @@ typedef struct spd_server_config {
     uint64_t min_scan_pairs;       /* while earlier scans are still running on the GPU, a router's queued
                                       pairs wait until this many are queued, its window can end, a close
                                       is requested or drain is called; an idle GPU takes whatever is
-                                      queued (0: the larger of 8 Mi and window_pairs / 4) */
+                                      queued (0: window_pairs, or 8 Mi without a window size: under
+                                      load a window is then scanned whole, into a fresh sketch, instead
+                                      of in parts that each read and rewrite the whole sketch) */
     const spd_tuning *tuning;      /* launch settings of the scans (NULL: the library's defaults); applied
                                       before the scratch of the largest group is reserved */
 } spd_server_config;

@@ -541,8 +541,8 @@ class Server:
         return dict(router=hdr.router, window=hdr.window, pairs=hdr.pairs, latency_ms=hdr.latency_ms,
                     n_super=hdr.n_super), sp
 
-    def replay(self, times, routers, tensors, flags=None) -> float:
-        """Submit tensors[i] for routers[i] at times[i] seconds (sorted) from a native loop."""
+    def schedule(self, times, routers, tensors, flags=None):
+        """The arrival array of replay (built ahead, so that replaying it costs no Python time)."""
         n = len(times)
         arr = (SpdArrival * max(1, n))()
         for i in range(n):
@@ -550,6 +550,12 @@ class Server:
             arr[i] = SpdArrival(float(times[i]), int(routers[i]), int(flags[i]) if flags is not None else 0,
                                 ptr or None, cnt)
             self._keep.append(tensors[i])
+        return arr, n
+
+    def replay(self, times, routers=None, tensors=None, flags=None) -> float:
+        """Submit tensors[i] for routers[i] at times[i] seconds (sorted) from a native loop; `times`
+        may instead be what schedule() returned."""
+        arr, n = times if routers is None else self.schedule(times, routers, tensors, flags)
         el = ctypes.c_double(0.0)
         self._check(lib().spd_server_replay(self.h, arr, n, ctypes.byref(el)))
         return el.value

@@ -2138,7 +2138,7 @@ spd_status spd_server_create(const spd_params *p, const spd_server_config *cfg, 
     S->cfg = *cfg;
     if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = 4ull << 30;
     if (!S->cfg.max_group_pairs) S->cfg.max_group_pairs = 64ull << 20;
-    if (!S->cfg.min_scan_pairs) S->cfg.min_scan_pairs = std::max<uint64_t>(8ull << 20, S->cfg.window_pairs / 4);
+    if (!S->cfg.min_scan_pairs) S->cfg.min_scan_pairs = S->cfg.window_pairs ? S->cfg.window_pairs : 8ull << 20;
     if (!S->cfg.max_group_batches) S->cfg.max_group_batches = 1024;
     S->cfg.max_group_batches = std::min<uint32_t>(S->cfg.max_group_batches, 4096);
     spd_status st = ctx_create(p, 0, 0, S->cfg.hbm_budget_bytes, &S->ctx);
