@@ -244,11 +244,9 @@ hipError_t launch_renormalize_u16(uint16_t *p, uint64_t n, uint16_t off, hipStre
 hipError_t launch_bit_view(const uint16_t *ts, uint64_t n_bits, uint16_t thr, uint32_t *out_words, hipStream_t s);
 
 struct CloseArgs {
-    const uint8_t *seav;
+    const uint8_t *seav;     // the SEAV as bits (sliding: the bit view of its counters)
     const uint32_t *ldca;
-    const uint16_t *seav_ts;
-    const uint16_t *ldca_ts;
-    const uint8_t *seav_at;
+    const uint16_t *ldca_ts;   // sliding: the LDCA's counters, read by the ULDC filter
     const uint8_t *ldca_at;
     uint32_t thr;        // sliding, 16-bit stamps: stamp threshold of the bit view
     uint32_t at_ct;      // sliding, AT pool: code of the current slice
@@ -261,7 +259,7 @@ struct CloseArgs {
     uint32_t n_rp;
     uint32_t list_stride;
     uint32_t qcap;
-    uint32_t stage_words;  // LDS words per wavefront holding one SEA (its bit view when sliding)
+    uint32_t stage_words;  // LDS words per wavefront holding one SEA
     uint32_t parts_log2;   // each SEA's candidates are searched by 2^parts_log2 wavefronts
 };
 hipError_t launch_close(const Consts &c, const CloseArgs &a, int mode, uint32_t block, uint32_t grid, hipStream_t s);

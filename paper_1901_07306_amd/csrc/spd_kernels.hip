@@ -1622,23 +1622,11 @@ __device__ __forceinline__ uint32_t at_active4(uint32_t w, const CloseArgs &a) {
     return r;
 }
 
-// One SEAV byte as bits: the byte itself, or the bit view of its 8 counters.
+// One SEAV byte as bits.  With counters (sliding window) the end of window reads a bit view of
+// the SEAV made by a streaming kernel just before it (a.seav), so every mode reads bytes here.
 template <int MODE>
 __device__ __forceinline__ uint32_t load_se(const CloseArgs &a, uint64_t byte) {
-    if (MODE == kCloseBits) return a.seav[byte];
-    uint32_t v = 0;
-    if (MODE == kCloseStamps) {
-        const u32x4 t = *reinterpret_cast<const u32x4 *>(a.seav_ts + byte * 8);   // 8 stamps
-        v = ts_bits2(t.x, a.thr) | ts_bits2(t.y, a.thr) << 2 | ts_bits2(t.z, a.thr) << 4 | ts_bits2(t.w, a.thr) << 6;
-    } else {
-        // the byte's eight bits in a fixed permuted order (counter 4h + j at bit 2j + h): every SEAV
-        // byte of the window is read the same way, so the weights and the AND of the rows used by
-        // the end of window are those of the canonical order
-        const uint64_t t = *reinterpret_cast<const uint64_t *>(a.seav_at + byte * 8);
-        const uint32_t x = (at_active4((uint32_t)t, a) >> 7) | (at_active4((uint32_t)(t >> 32), a) >> 6);
-        v = (x | x >> 6 | x >> 12 | x >> 18) & 0xFFu;
-    }
-    return v;
+    return a.seav[byte];
 }
 
 // The counters behind one LDCA word (word < 2^27: a sketch has fewer than 2^32 bits), as loaded:

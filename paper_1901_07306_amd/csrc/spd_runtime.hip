@@ -49,6 +49,7 @@ struct CloseBuf {
     uint32_t *rec = nullptr;          // counters + 4
     uint32_t rec_cap = 0;
     uint32_t *h_counters = nullptr;   // pinned and mapped, same layout, kRecChunk records
+    uint8_t *seav_bits = nullptr;     // sliding: the bit view of the SEAV counters the close reads
     uint32_t *d_counters = nullptr;   // h_counters' device address
     uint32_t *h_rec = nullptr;        // pinned, all records when there are more than kRecChunk
     uint32_t h_rec_cap = 0;
@@ -1037,6 +1038,10 @@ spd_status close_buf_init(spd_ctx *ctx, CloseBuf &cb) {
         spd_status st = close_rec_alloc(ctx, cb, kRecInit);
         if (st) return st;
     }
+    if (ctx->sliding && !cb.seav_bits) {
+        spd_status st = dev_alloc(ctx, &cb.seav_bits, ctx->seav_alloc);
+        if (st) return st;
+    }
     if (!cb.h_counters) {
         SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_counters, 16 + (uint64_t)kRecChunk * 8, hipHostMallocMapped));
         SPD_HIP(ctx, hipHostGetDevicePointer((void **)&cb.d_counters, cb.h_counters, 0));
@@ -1049,6 +1054,7 @@ void close_buf_free(spd_ctx *ctx, CloseBuf &cb) {
     cb.graph = nullptr;
     dev_free(ctx, &cb.counters, 16 + (uint64_t)cb.rec_cap * 8);
     cb.rec = nullptr;
+    dev_free(ctx, &cb.seav_bits, ctx->seav_alloc);
     if (cb.h_counters) (void)hipHostFree(cb.h_counters);
     if (cb.h_rec) (void)hipHostFree(cb.h_rec);
     cb.h_counters = nullptr;
@@ -1062,11 +1068,9 @@ int close_mode(const spd_ctx *ctx) { return ctx->at ? kCloseAt : ctx->sliding ? 
 // Arguments and launch shape of the end-of-window kernel for one slot.
 spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArgs *a, uint32_t *block, uint32_t *grid) {
     *a = CloseArgs{};
-    a->seav = sl.seav;
+    a->seav = ctx->sliding ? cb.seav_bits : sl.seav;
     a->ldca = sl.ldca;
-    a->seav_ts = sl.seav_ts;
     a->ldca_ts = sl.ldca_ts;
-    a->seav_at = sl.seav_at;
     a->ldca_at = sl.ldca_at;
     a->at_ct = at_code(ctx->slice);
     a->at_k = ctx->K;
@@ -1118,6 +1122,10 @@ spd_status close_launch_ops(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStrea
     spd_status st = close_args(ctx, sl, cb, &a, &block, &grid);
     if (st) return st;
     ProfScope ps(ctx, SPD_K_CLOSE, s);
+    if (ctx->at)   // the SEAV's bit view first, streamed at full bandwidth (canonical bit order)
+        SPD_HIP(ctx, launch_bit_view_at(sl.seav_at, ctx->seav_alloc * 8, a.at_ct, ctx->K, reinterpret_cast<uint32_t *>(cb.seav_bits), s));
+    else if (ctx->sliding)
+        SPD_HIP(ctx, launch_bit_view(sl.seav_ts, ctx->seav_alloc * 8, (uint16_t)a.thr, reinterpret_cast<uint32_t *>(cb.seav_bits), s));
     SPD_HIP(ctx, launch_close(ctx->c, a, close_mode(ctx), block, grid, s));
     return SPD_OK;
 }
