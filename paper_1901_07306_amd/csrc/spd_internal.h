@@ -143,8 +143,14 @@ hipError_t launch_scan_direct(const Consts &c, const BatchDesc *batches, uint32_
                               uint32_t block, uint32_t grid, bool seav_lds, hipStream_t s);
 // Sliding scan: every bit the discrete scan would set receives `value` (a 16-bit stamp, or an AT
 // code when at is set).
+// Optional timing of one kernel launch: events that the dispatch itself stamps at the kernel's start
+// and end (no separate event packets on the stream).  Null events: an ordinary launch.
+struct KTiming {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
 hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
-                             uint32_t value, bool at, uint32_t block, uint32_t grid, hipStream_t s);
+                             uint32_t value, bool at, uint32_t block, uint32_t grid, hipStream_t s, KTiming kt = {});
 // AT pool maintenance: the counters of bytes [lo, hi) of each of n pools (hi <= pool bytes, lo and
 // hi multiples of 16) that are expired at the slice of code ct are set to that slice's expired code.
 hipError_t launch_at_sweep(uint8_t *const *pools, uint32_t n, uint64_t lo, uint64_t hi, uint32_t ct, uint32_t K,
@@ -221,7 +227,7 @@ __host__ __device__ __forceinline__ uint64_t chunk_at(const RegionArgs &ra, uint
     return ra.slot_base[si] + (uint64_t)cc * ra.chunk_words;
 }
 hipError_t launch_region(const Consts &c, const BinGeometry &g, const BatchList &bl, uint32_t n_tiles,
-                         const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra, hipStream_t s);
+                         const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra, hipStream_t s, KTiming kt = {});
 struct ApplySlot {
     uint32_t *ldca;
     uint32_t *seav_w;
@@ -234,7 +240,7 @@ hipError_t launch_apply(const BinGeometry &g, const ApplySlot *slots, uint32_t n
 hipError_t launch_apply_bm(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const uint32_t *items,
                            const uint32_t *base, uint32_t block, uint32_t unroll, hipStream_t s);
 hipError_t launch_apply_rg(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const ChunkTable &ct,
-                           const RegionArgs &ra, uint32_t block, uint32_t unroll, hipStream_t s);
+                           const RegionArgs &ra, uint32_t block, uint32_t unroll, hipStream_t s, KTiming kt = {});
 hipError_t launch_spill(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const RegionArgs &ra,
                         hipStream_t s);
 hipError_t launch_or_merge(uint32_t *dst, const uint32_t *const *src, uint32_t n_src, uint64_t n_words, hipStream_t s);

@@ -15,6 +15,8 @@
 // End of window (Sections 3.2-3.3): k_close gives one wavefront per SEA (one RP): hot-SE lists
 // by ballot, the candidate product with Eq. 3 consistency and the SEU weight test, then the
 // ULDC of each candidate (AND over LR rows, popcount by wavefront reduction).
+#include <hip/hip_ext.h>
+
 #include "spd_internal.h"
 
 namespace spd {
@@ -233,15 +235,15 @@ __global__ __launch_bounds__(1024) void k_scan_stamp(Consts c, BatchTable bt, Sl
 }
 
 hipError_t launch_scan_stamp(const Consts &c, const BatchDesc *batches, uint32_t n_batches, const SlotPtrs *slots,
-                             uint32_t value, bool at, uint32_t block, uint32_t grid, hipStream_t s) {
+                             uint32_t value, bool at, uint32_t block, uint32_t grid, hipStream_t s, KTiming kt) {
     BatchTable bt{};
     SlotTable st{};
     if (n_batches > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
     for (uint32_t i = 0; i < n_batches; ++i) bt.b[i] = batches[i];
     bt.n = n_batches;
     for (int i = 0; i < kMaxGroup; ++i) st.s[i] = slots[i];
-    if (at) hipLaunchKernelGGL(k_scan_stamp<uint8_t>, dim3(grid), dim3(block), 0, s, c, bt, st, value);
-    else hipLaunchKernelGGL(k_scan_stamp<uint16_t>, dim3(grid), dim3(block), 0, s, c, bt, st, value);
+    if (at) hipExtLaunchKernelGGL(k_scan_stamp<uint8_t>, dim3(grid), dim3(block), 0, s, kt.start, kt.stop, 0, c, bt, st, value);
+    else hipExtLaunchKernelGGL(k_scan_stamp<uint16_t>, dim3(grid), dim3(block), 0, s, kt.start, kt.stop, 0, c, bt, st, value);
     return hipGetLastError();
 }
 
@@ -1026,11 +1028,13 @@ __global__ __launch_bounds__(BLOCK) void k_region(Consts c, BinGeometry g, Batch
 
 template <int LR>
 static hipError_t launch_region_lr(const Consts &c, const BinGeometry &g, const BatchList &bl, const SlotTable &st,
-                                   const ChunkTable &ct, const RegionArgs &ra, uint32_t n_tiles, hipStream_t s) {
+                                   const ChunkTable &ct, const RegionArgs &ra, uint32_t n_tiles, hipStream_t s,
+                                   KTiming kt) {
     const uint32_t ppt = g.tile_pairs / g.block;
 #define SPD_RG_CASE(B, P)                                                                                        \
     else if (g.block == B && ppt == P)                                                                         \
-        hipLaunchKernelGGL((k_region<LR, P, B>), dim3(n_tiles), dim3(B), g.lds_bytes, s, c, g, bl, st, ct, ra);
+        hipExtLaunchKernelGGL((k_region<LR, P, B>), dim3(n_tiles), dim3(B), g.lds_bytes, s, kt.start, kt.stop, 0, c, g, \
+                              bl, st, ct, ra);
     if (false) {
     }
     SPD_RG_CASE(1024, 16) SPD_RG_CASE(1024, 8) SPD_RG_CASE(1024, 4) SPD_RG_CASE(512, 16) SPD_RG_CASE(512, 8)
@@ -1041,15 +1045,15 @@ static hipError_t launch_region_lr(const Consts &c, const BinGeometry &g, const 
 }
 
 hipError_t launch_region(const Consts &c, const BinGeometry &g, const BatchList &bl, uint32_t n_tiles,
-                         const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra, hipStream_t s) {
+                         const ChunkTable &ct, const SlotPtrs *slots, const RegionArgs &ra, hipStream_t s, KTiming kt) {
     if (bl.n == 0 || n_tiles == 0 || (!bl.b && bl.n > kInlineBatches)) return hipErrorInvalidValue;
     SlotTable st{};
     for (uint32_t i = 0; i < ct.n; ++i) st.s[i] = slots[i];
     switch (c.lr) {
-    case 1: return launch_region_lr<1>(c, g, bl, st, ct, ra, n_tiles, s);
-    case 2: return launch_region_lr<2>(c, g, bl, st, ct, ra, n_tiles, s);
-    case 3: return launch_region_lr<3>(c, g, bl, st, ct, ra, n_tiles, s);
-    case 4: return launch_region_lr<4>(c, g, bl, st, ct, ra, n_tiles, s);
+    case 1: return launch_region_lr<1>(c, g, bl, st, ct, ra, n_tiles, s, kt);
+    case 2: return launch_region_lr<2>(c, g, bl, st, ct, ra, n_tiles, s, kt);
+    case 3: return launch_region_lr<3>(c, g, bl, st, ct, ra, n_tiles, s, kt);
+    case 4: return launch_region_lr<4>(c, g, bl, st, ct, ra, n_tiles, s, kt);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1139,14 +1143,16 @@ __global__ __launch_bounds__(BLOCK) void k_apply_rg(BinGeometry g, ApplyTable at
 
 template <int U>
 static void launch_apply_rg_u(const BinGeometry &g, const ApplyTable &at, const ChunkTable &ct, const RegionArgs &ra,
-                              dim3 grid, uint32_t lds, uint32_t block, hipStream_t s) {
-    if (block == 1024) hipLaunchKernelGGL((k_apply_rg<1024, U>), grid, dim3(1024), lds, s, g, at, ct, ra);
-    else if (block == 512) hipLaunchKernelGGL((k_apply_rg<512, U>), grid, dim3(512), lds, s, g, at, ct, ra);
-    else hipLaunchKernelGGL((k_apply_rg<256, U>), grid, dim3(256), lds, s, g, at, ct, ra);
+                              dim3 grid, uint32_t lds, uint32_t block, hipStream_t s, KTiming kt) {
+    if (block == 1024)
+        hipExtLaunchKernelGGL((k_apply_rg<1024, U>), grid, dim3(1024), lds, s, kt.start, kt.stop, 0, g, at, ct, ra);
+    else if (block == 512)
+        hipExtLaunchKernelGGL((k_apply_rg<512, U>), grid, dim3(512), lds, s, kt.start, kt.stop, 0, g, at, ct, ra);
+    else hipExtLaunchKernelGGL((k_apply_rg<256, U>), grid, dim3(256), lds, s, kt.start, kt.stop, 0, g, at, ct, ra);
 }
 
 hipError_t launch_apply_rg(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const ChunkTable &ct,
-                           const RegionArgs &ra, uint32_t block, uint32_t unroll, hipStream_t s) {
+                           const RegionArgs &ra, uint32_t block, uint32_t unroll, hipStream_t s, KTiming kt) {
     ApplyTable at{};
     if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup || ct.n != n_slots) return hipErrorInvalidValue;
     if (block != 1024 && block != 512 && block != 256) return hipErrorInvalidConfiguration;
@@ -1154,9 +1160,9 @@ hipError_t launch_apply_rg(const BinGeometry &g, const ApplySlot *slots, uint32_
     const uint32_t lds = (1u << (g.S - 5)) * 4u;
     dim3 grid(n_slots * g.nb);
     switch (unroll) {
-    case 8: launch_apply_rg_u<4>(g, at, ct, ra, grid, lds, block, s); break;
-    case 16: launch_apply_rg_u<8>(g, at, ct, ra, grid, lds, block, s); break;
-    case 32: launch_apply_rg_u<16>(g, at, ct, ra, grid, lds, block, s); break;
+    case 8: launch_apply_rg_u<4>(g, at, ct, ra, grid, lds, block, s, kt); break;
+    case 16: launch_apply_rg_u<8>(g, at, ct, ra, grid, lds, block, s, kt); break;
+    case 32: launch_apply_rg_u<16>(g, at, ct, ra, grid, lds, block, s, kt); break;
     default: return hipErrorInvalidConfiguration;
     }
     return hipGetLastError();

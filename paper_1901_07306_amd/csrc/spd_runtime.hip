@@ -328,6 +328,27 @@ struct ProfScope {
     }
 };
 
+// Times one kernel launch, when profiling is on, with events that the dispatch stamps itself at
+// the kernel's start and end (no event packets of their own between the kernels of a window).
+struct ProfKernel {
+    spd_ctx *ctx;
+    int kind;
+    KTiming kt{};
+    ProfKernel(spd_ctx *c, int k) : ctx(c), kind(k) {
+        if (ctx->prof_on && ((ctx->prof_mask >> k) & 1u)) {
+            kt.start = prof_event(ctx);
+            kt.stop = kt.start ? prof_event(ctx) : nullptr;
+            if (!kt.stop && kt.start) {
+                ctx->prof_pool.push_back(kt.start);
+                kt.start = nullptr;
+            }
+        }
+    }
+    ~ProfKernel() {
+        if (kt.start) ctx->prof_pending.push_back({kind, kt.start, kt.stop});
+    }
+};
+
 void prof_harvest(spd_ctx *ctx) {
     for (auto &p : ctx->prof_pending) {
         float ms = 0.f;
@@ -682,8 +703,8 @@ spd_status region_launch_at(spd_ctx *ctx, const BinGeometry &g, const BatchDesc 
     }
     *rs.aux_zero = false;   // until the launch's apply and spill phases are enqueued
     {
-        ProfScope ps(ctx, SPD_K_BIN, s);
-        SPD_HIP(ctx, launch_region(ctx->c, g, bl, tiles, ct, sp, ra, s));
+        ProfKernel pk(ctx, SPD_K_BIN);
+        SPD_HIP(ctx, launch_region(ctx->c, g, bl, tiles, ct, sp, ra, s, pk.kt));
         if (!inl) {
             // the staging slot may be rewritten once the binning kernel has read it
             SPD_HIP(ctx, hipEventRecord(ctx->bd_ev[ctx->bd_next], s));
@@ -691,8 +712,8 @@ spd_status region_launch_at(spd_ctx *ctx, const BinGeometry &g, const BatchDesc 
         }
     }
     {
-        ProfScope ps(ctx, SPD_K_APPLY, s);
-        SPD_HIP(ctx, launch_apply_rg(g, as, nsl, ct, ra, ctx->tune.apply_block, ctx->tune.apply_unroll, s));
+        ProfKernel pk(ctx, SPD_K_APPLY);
+        SPD_HIP(ctx, launch_apply_rg(g, as, nsl, ct, ra, ctx->tune.apply_block, ctx->tune.apply_unroll, s, pk.kt));
     }
     {
         ProfScope ps(ctx, SPD_K_SPILL, s);
@@ -755,9 +776,9 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             uint32_t grid = (uint32_t)std::max<uint64_t>(
                 1, std::min<uint64_t>(want, (uint64_t)ctx->tune.direct_grid_per_cu * ctx->n_cu));
             if (stamp) {
-                ProfScope ps(ctx, SPD_K_STAMP, s);
+                ProfKernel pk(ctx, SPD_K_STAMP);
                 const uint32_t value = ctx->at ? at_code(ctx->slice) : (ctx->slice + 1) & 0xFFFFu;
-                SPD_HIP(ctx, launch_scan_stamp(ctx->c, bd, nbd, sp, value, ctx->at, block, grid, s));
+                SPD_HIP(ctx, launch_scan_stamp(ctx->c, bd, nbd, sp, value, ctx->at, block, grid, s, pk.kt));
             } else {
                 const bool lds = ctx->tune.seav_lds && nsl == 1 && ctx->d.seav_bytes <= 64 * 1024;
                 ProfScope ps(ctx, SPD_K_DIRECT, s);
