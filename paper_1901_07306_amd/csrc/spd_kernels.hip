@@ -258,6 +258,24 @@ struct CPoolTable {
 // Byte k of a 16-byte vector.
 __device__ __forceinline__ uint32_t byte_of(const u32x4 &v, uint32_t k) { return (v[k >> 2] >> (8 * (k & 3))) & 0xFFu; }
 
+// Activity of the four AT counters packed in one 32-bit word, four at a time (SIMD within a
+// register): bit 7 of byte j of the result is set iff counter j is active, i.e. its age
+// (ct - v) mod 256 is below K.  The per-byte difference is taken without borrows between bytes;
+// the per-byte compare with K needs K <= 128, so larger windows decode byte by byte.
+__device__ __forceinline__ uint32_t at_active_bytes(uint32_t w, uint32_t ct, uint32_t K) {
+    constexpr uint32_t H = 0x80808080u, L = 0x7F7F7F7Fu;
+    if (K <= 128u) {
+        const uint32_t ct4 = ct * 0x01010101u, k4 = K * 0x01010101u;
+        const uint32_t e = ((ct4 | H) - (w & L)) ^ ((ct4 ^ ~w) & H);   // (ct - v) mod 256 per byte
+        const uint32_t d = ((e & L) | H) - k4;                          // top bit: low 7 bits of e >= K
+        return ~(e | d) & H;
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) r |= at_active((w >> (8 * j)) & 0xFFu, ct, K) << (8 * j + 7);
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_at_sweep(PoolTable pt, uint32_t n, uint64_t lo16, uint64_t hi16, uint32_t ct,
                                                   uint32_t K) {
     const uint64_t stride = (uint64_t)gridDim.x * 256;
@@ -337,9 +355,11 @@ __global__ __launch_bounds__(256) void k_bit_view_at(const uint8_t *__restrict__
         const u32x4 a = reinterpret_cast<const u32x4 *>(at)[2 * w], b = reinterpret_cast<const u32x4 *>(at)[2 * w + 1];
         uint32_t v = 0;
 #pragma unroll
-        for (uint32_t j = 0; j < 16; ++j) {
-            v |= at_active(byte_of(a, j), ct, K) << j;
-            v |= at_active(byte_of(b, j), ct, K) << (16 + j);
+        for (uint32_t q = 0; q < 4; ++q) {
+            // counters 4q..4q+3 of each vector: activity bits at 0, 8, 16, 24, gathered into 4 bits
+            const uint32_t ma = at_active_bytes(a[q], ct, K) >> 7, mb = at_active_bytes(b[q], ct, K) >> 7;
+            v |= ((ma | ma >> 7 | ma >> 14 | ma >> 21) & 0xFu) << (4 * q);
+            v |= ((mb | mb >> 7 | mb >> 14 | mb >> 21) & 0xFu) << (16 + 4 * q);
         }
         out[w] = v;
     }
@@ -1610,23 +1630,8 @@ __device__ __forceinline__ uint32_t ts_bits2(uint32_t w, uint32_t thr) {
     return ((w & 0xFFFFu) >= thr ? 1u : 0u) | ((w >> 16) >= thr ? 2u : 0u);
 }
 
-// Activity of the four AT counters packed in one 32-bit word, four at a time (SIMD within a
-// register): bit 7 of byte j of the result is set iff counter j is active, i.e. its age
-// (ct - v) mod 256 is below K.  The per-byte difference is taken without borrows between bytes;
-// the per-byte compare with K needs K <= 128, so larger windows decode byte by byte.
-__device__ __forceinline__ uint32_t at_active4(uint32_t w, const CloseArgs &a) {
-    constexpr uint32_t H = 0x80808080u, L = 0x7F7F7F7Fu;
-    if (a.at_k <= 128u) {
-        const uint32_t ct4 = a.at_ct * 0x01010101u, k4 = a.at_k * 0x01010101u;
-        const uint32_t e = ((ct4 | H) - (w & L)) ^ ((ct4 ^ ~w) & H);   // (ct - v) mod 256 per byte
-        const uint32_t d = ((e & L) | H) - k4;                          // top bit: low 7 bits of e >= K
-        return ~(e | d) & H;
-    }
-    uint32_t r = 0;
-#pragma unroll
-    for (uint32_t j = 0; j < 4; ++j) r |= at_active((w >> (8 * j)) & 0xFFu, a.at_ct, a.at_k) << (8 * j + 7);
-    return r;
-}
+// at_active_bytes with the close's window.
+__device__ __forceinline__ uint32_t at_active4(uint32_t w, const CloseArgs &a) { return at_active_bytes(w, a.at_ct, a.at_k); }
 
 // One SEAV byte as bits.  With counters (sliding window) the end of window reads a bit view of
 // the SEAV made by a streaming kernel just before it (a.seav), so every mode reads bytes here.
