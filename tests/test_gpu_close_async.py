@@ -8,7 +8,10 @@ the oracle.
 * Every pending slot in use at once, collected in reverse order; one more begin is refused; a
   ticket is collected only once.
 * The merged sketch, an empty window, and a sliding window (nothing reset there) give the same
-  report as the blocking close.
+  report as the blocking close; sliding reports collected one slice behind (the next slide, its AT
+  maintenance and its scan enqueued first) are those of their own windows.
+* A window with more super points than a pending close holds: SPD_E_TRUNCATED with their number,
+  then room in every pending close.
 """
 import numpy as np
 import pytest
@@ -147,3 +150,32 @@ def test_pending_close_record_overflow_then_room():
             assert_same_report(det.close_end(t, cap=200_000), want, f"again {k}")
     finally:
         det.close()
+
+
+def test_sliding_reports_collected_one_slice_behind():
+    """Sliding window as a capture loop runs it: each slice's close is begun, the next slice is
+    slid to and scanned (AT maintenance included), and only then is the previous report collected;
+    every report must be the oracle's for the window that ended at its own slice."""
+    K = 6
+    slices = windows(306, 14, heavy=5, peers=200, noise=30_000)
+    for counter in (spd.SLIDING_AT, spd.SLIDING_STAMPS):
+        log(f"case sliding reports one slice behind, counter {counter}")
+        sp = st.MethodParams(theta=256, r=10, sr=4, a=2, log2k=10, lr=2, log2lc=10, window_slices=K,
+                             sliding_counter=counter, hash_seed=93)
+        det = spd.Detector(spd.params_from(sp))
+        try:
+            reps, prev = [], None
+            for t, w in enumerate(slices):
+                if t:
+                    det.slide()
+                det.scan(0, to_dev(w))
+                tk = det.close_begin(0)
+                if prev is not None:
+                    reps.append(det.close_end(prev))
+                prev = tk
+            reps.append(det.close_end(prev))
+            for t, got in enumerate(reps):
+                want = oracle_sketch(sp, np.concatenate(slices[max(0, t - K + 1): t + 1])).detect()
+                assert_same_report(got, want, f"counter {counter} slice {t}")
+        finally:
+            det.close()
