@@ -227,8 +227,9 @@ def bench_plain_1m(spd, torch, np, st, at, steps, warmup):
 
 
 def bench_routers(spd, torch, np, st, at, steps, warmup):
-    """8 routers x 16 Mi pairs: one fused scan call over the 8 routers' batches, OR merge into the
-    global sketch, global end of window, each router's sketch reset for its next window."""
+    """8 routers x 16 Mi pairs: one fused scan call over the 8 routers' batches that also ORs them
+    into the global sketch (spd_scan_batches_merge: the merge done by the apply phase), global end
+    of window, each router's sketch reset for its next window."""
     w = st.CONFIGS["routers_8x16m"]
     g0 = time.perf_counter()
     win = st.gen_routers(w)
@@ -238,11 +239,10 @@ def bench_routers(spd, torch, np, st, at, steps, warmup):
     params = spd.params_from(w.params)
     det = spd.Detector(params, n_routers=R)
     batches = [(r, xs[r]) for r in range(R)]
-    tuned = at.autotune(det, xs[0], quick=True, batches=batches)   # timed on the fused call itself
+    tuned = at.autotune(det, xs[0], quick=True, batches=batches, merge=True)   # timed on the fused call itself
 
     def step():
-        det.scan_batches(batches)
-        det.merge(list(range(R)))
+        det.scan_batches(batches, merge=True)
         rep = det.close_window(spd.GLOBAL)
         for r in range(R):
             det.reset(r)
@@ -276,7 +276,8 @@ def bench_routers(spd, torch, np, st, at, steps, warmup):
          "tuning": tuned, "reported_super_points": int(len(rec)),
          "workload": "routers_8x16m: 8 routers x 16Mi pairs, 40% of 4M sources at >=2 routers, 300 planted "
                      "split over routers; fused scan of the 8 routers + OR merge + global end of window",
-         "step": "scan_batches(8 routers) + merge + close(global) + reset(routers)"}
+         "step": "scan_batches_merge(8 routers: scan + OR merge into the global sketch) + close(global) + "
+                 "reset(routers)"}
     del xs
     return e, win, rec
 

@@ -203,6 +203,12 @@ spd_status spd_scan_noalloc(spd_ctx *ctx, uint32_t router, const uint32_t *pairs
  * calling spd_scan on each batch). */
 spd_status spd_scan_batches(spd_ctx *ctx, const spd_batch *batches, uint32_t n_batches, void *stream);
 
+/* spd_scan_batches, then spd_merge of the routers the batches name: the global sketch := OR of
+ * their sketches (Section 4.2).  When every named router gets pairs here and the call is one launch
+ * of the region layout, the merge is done by the apply phase itself (no pass over the router
+ * sketches); otherwise an ordinary spd_merge follows.  Same results either way. */
+spd_status spd_scan_batches_merge(spd_ctx *ctx, const spd_batch *batches, uint32_t n_batches, void *stream);
+
 /* Merge (Section 4.2): global sketch = bitwise OR of the listed routers' sketches (sliding mode:
  * element-wise maximum of time stamps, whose bit view is the OR).  The previous global content
  * is replaced.  Order-free; listing a router twice changes nothing. */

@@ -90,7 +90,7 @@ class SpdServerStats(ctypes.Structure):
 
 RECORD = np.dtype([("ip", "<u4"), ("z0", "<u4"), ("est", "<u4"), ("flags", "<u4")])
 
-EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_noalloc", "spd_scan_host", "spd_scan_batches", "spd_merge",
+EXPORTED = ["spd_derive", "spd_create", "spd_destroy", "spd_scan", "spd_scan_noalloc", "spd_scan_host", "spd_scan_batches", "spd_scan_batches_merge", "spd_merge",
             "spd_close_window", "spd_close_begin", "spd_close_end", "spd_reset", "spd_slide", "spd_export", "spd_import", "spd_export_stamps",
             "spd_current_slice", "spd_get_tuning", "spd_set_tuning", "spd_get_stats", "spd_strerror",
             "spd_last_error", "spd_profile_enable", "spd_profile_select", "spd_get_profile", "spd_server_create", "spd_server_submit",
@@ -148,6 +148,7 @@ def lib(require_torch: bool = True) -> ctypes.CDLL:
         "spd_scan_host": (i32, [vp, u32, vp, u64, u32, u64, vp]),
         "spd_scan_noalloc": (i32, [vp, u32, vp, u64, u32, vp]),
         "spd_scan_batches": (i32, [vp, P(SpdBatch), u32, vp]),
+        "spd_scan_batches_merge": (i32, [vp, P(SpdBatch), u32, vp]),
         "spd_merge": (i32, [vp, P(u32), u32, vp]),
         "spd_close_window": (i32, [vp, i32, P(SpdSuperpoint), u32, P(u32), vp]),
         "spd_close_begin": (i32, [vp, i32, vp, P(u32)]),
@@ -287,8 +288,9 @@ def spd_scan_host(ctx: int, router: int, pairs, flags: int = 0, chunk_pairs: int
     _check(lib().spd_scan_host(ctx, router, ptr or None, n, flags, chunk_pairs, _stream_ptr(stream)), ctx)
 
 
-def spd_scan_batches(ctx: int, batches: Iterable[Tuple], stream=None) -> None:
-    """batches: (router, pairs) or (router, pairs, flags) with flags BATCH_DST for destination-keyed."""
+def spd_scan_batches(ctx: int, batches: Iterable[Tuple], stream=None, merge: bool = False) -> None:
+    """batches: (router, pairs) or (router, pairs, flags) with flags BATCH_DST for destination-keyed.
+    merge: then the global sketch := OR of the routers named (spd_scan_batches_merge)."""
     items = []
     for b in batches:
         router, pairs = b[0], b[1]
@@ -296,7 +298,8 @@ def spd_scan_batches(ctx: int, batches: Iterable[Tuple], stream=None) -> None:
         ptr, n = _pairs_ptr(pairs)
         items.append(SpdBatch(router, flags, ptr or None, n))
     arr = (SpdBatch * max(1, len(items)))(*items)
-    _check(lib().spd_scan_batches(ctx, arr, len(items), _stream_ptr(stream)), ctx)
+    fn = lib().spd_scan_batches_merge if merge else lib().spd_scan_batches
+    _check(fn(ctx, arr, len(items), _stream_ptr(stream)), ctx)
 
 
 def spd_merge(ctx: int, routers: Sequence[int], stream=None) -> None:
@@ -448,8 +451,8 @@ class Detector:
         """Pairs in host memory (numpy array or CPU tensor), copied in chunks overlapping the scan."""
         spd_scan_host(self.ctx, router, pairs, flags, chunk_pairs, stream)
 
-    def scan_batches(self, batches, stream=None):
-        spd_scan_batches(self.ctx, batches, stream)
+    def scan_batches(self, batches, stream=None, merge=False):
+        spd_scan_batches(self.ctx, batches, stream, merge)
 
     def merge(self, routers, stream=None):
         spd_merge(self.ctx, routers, stream)

@@ -18,13 +18,14 @@ TUNED_FIELDS = ("bin_mode", "bucket_bits", "tile_pairs", "bin_block", "apply_blo
                 "direct_block", "direct_grid_per_cu", "seav_lds", "direct_max_pairs")
 
 
-def _scan_ms(det, x, reps: int, batches=None) -> float:
+def _scan_ms(det, x, reps: int, batches=None, merge: bool = False) -> float:
     """Device time of one scan of x into router 0, or of one fused call over `batches`
-    ((router, tensor) pairs), averaged over reps; the routers are reset afterwards."""
+    ((router, tensor) pairs; with `merge`, the call that also ORs them into the global sketch, whose
+    merge time then counts), averaged over reps; the routers are reset afterwards."""
     det.profile_enable(True)
     for _ in range(reps):
         if batches:
-            det.scan_batches(batches)
+            det.scan_batches(batches, merge=merge)
         else:
             det.scan(0, x)
     prof = det.profile()
@@ -34,7 +35,7 @@ def _scan_ms(det, x, reps: int, batches=None) -> float:
             det.reset(r)
     else:
         det.close_window(0)
-    return sum(prof[k][1] for k in SCAN_KINDS) / reps
+    return sum(prof[k][1] for k in SCAN_KINDS + (("merge",) if merge else ())) / reps
 
 
 def candidate_settings(quick: bool = False) -> List[dict]:
@@ -63,7 +64,8 @@ def _apply(det, settings: dict) -> None:
     det.tuning = t
 
 
-def tune_binned(det, x, reps: int = 3, quick: bool = False, batches=None) -> Tuple[dict, List[Tuple[dict, float]]]:
+def tune_binned(det, x, reps: int = 3, quick: bool = False, batches=None,
+                merge: bool = False) -> Tuple[dict, List[Tuple[dict, float]]]:
     """Fastest binned-scan setting for batch x on detector det (router 0 is used and reset), or for
     the fused call over `batches` when given (the routers named there are reset)."""
     base = det.tuning
@@ -73,8 +75,8 @@ def tune_binned(det, x, reps: int = 3, quick: bool = False, batches=None) -> Tup
             _apply(det, dict(cand, direct_max_pairs=0))
         except Exception:
             continue
-        _scan_ms(det, x, 1, batches)   # warm-up (scratch growth)
-        table.append((cand, _scan_ms(det, x, reps, batches)))
+        _scan_ms(det, x, 1, batches, merge)   # warm-up (scratch growth)
+        table.append((cand, _scan_ms(det, x, reps, batches, merge)))
     det.tuning = base
     best = min(table, key=lambda e: e[1])[0]
     return best, table
@@ -115,15 +117,16 @@ def crossover(det, x, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22), reps:
     return best
 
 
-def autotune(det, x, key: Optional[tuple] = None, quick: bool = False, batches=None) -> dict:
+def autotune(det, x, key: Optional[tuple] = None, quick: bool = False, batches=None, merge: bool = False) -> dict:
     """Tune det for batches like x and apply the result.  With `batches` ((router, tensor) pairs of
-    one fused call), the binned settings are those of that fused call; the direct kernel's shape and
+    one fused call; `merge`: the call that also merges them into the global sketch), the binned
+    settings are those of that fused call; the direct kernel's shape and
     the direct/binned crossover are still tuned on x.  Returns the chosen settings; the timing tables
     are kept in the cache entry (``last_tables(key)``)."""
     import torch
-    key = key or cache_key(det, x, batches)
+    key = key or cache_key(det, x, batches, merge)
     if key not in _CACHE:
-        b, tb = tune_binned(det, x, quick=quick, batches=batches)
+        b, tb = tune_binned(det, x, quick=quick, batches=batches, merge=merge)
         d, td = tune_direct(det, x[: min(x.shape[0], 1 << 20)])
         cross = crossover(det, x)
         _CACHE[key] = dict(settings=dict(b, **d, direct_max_pairs=cross), binned=tb, direct=td,
@@ -132,12 +135,12 @@ def autotune(det, x, key: Optional[tuple] = None, quick: bool = False, batches=N
     return dict(_CACHE[key]["settings"])
 
 
-def cache_key(det, x, batches=None) -> tuple:
+def cache_key(det, x, batches=None, merge: bool = False) -> tuple:
     import torch
     p = det.params
     fused = tuple((int(r), int(t.shape[0])) for r, t in batches) if batches else ()
     return (torch.cuda.get_device_name(0), tuple(p.hash_mul[:3]), p.r, p.sr, p.log2k, p.lr, p.log2lc,
-            int(x.shape[0]), fused)
+            int(x.shape[0]), fused, bool(merge))
 
 
 def last_tables(key: tuple) -> dict:

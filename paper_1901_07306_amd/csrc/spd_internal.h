@@ -241,8 +241,13 @@ hipError_t launch_apply_bm(const BinGeometry &g, const ApplySlot *slots, uint32_
                            const uint32_t *base, uint32_t block, uint32_t unroll, hipStream_t s);
 hipError_t launch_apply_rg(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const ChunkTable &ct,
                            const RegionArgs &ra, uint32_t block, uint32_t unroll, hipStream_t s, KTiming kt = {});
+// The apply phase with the router OR merge fused in: the global sketch (its LDCA and SEAV) :=
+// OR of the launch's slots; 1024-lane workgroups, buckets of at most 2^20 bits.
+hipError_t launch_apply_rg_merge(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const ChunkTable &ct,
+                                 const RegionArgs &ra, const ApplySlot &global, uint32_t unroll, hipStream_t s,
+                                 KTiming kt = {});
 hipError_t launch_spill(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const RegionArgs &ra,
-                        hipStream_t s);
+                        hipStream_t s, const ApplySlot *global = nullptr);
 hipError_t launch_or_merge(uint32_t *dst, const uint32_t *const *src, uint32_t n_src, uint64_t n_words, hipStream_t s);
 hipError_t launch_max_merge_u16(uint16_t *dst, const uint16_t *const *src, uint32_t n_src, uint64_t n_elems,
                                 hipStream_t s);

@@ -1104,16 +1104,17 @@ hipError_t launch_clear(const ClearList &clear, hipStream_t s) {
 // Apply phase of the region layout: one workgroup per (slot, bucket) ORs the used part of the
 // bucket's region in each of the slot's chunks into an LDS bitmap.  Work is split into pieces of
 // 64 * U words (one per wavefront at a time); a piece past its region's fill is skipped.
+// Bucket b of slot si: loaded into the LDS bitmap bm (zero for a fresh slot's LDCA bucket), the
+// filled part of the bucket's region in every chunk of the slot applied with LDS atomicOr, the
+// region counters read zeroed for the next launch, the bitmap stored back.  Ends with bm complete
+// and visible to the whole workgroup.
 template <int BLOCK, int U>
-__global__ __launch_bounds__(BLOCK) void k_apply_rg(BinGeometry g, ApplyTable at, ChunkTable ct, RegionArgs ra) {
-    extern __shared__ uint32_t bm[];
+__device__ __forceinline__ void apply_bucket(const BinGeometry &g, const ApplySlot &A, uint32_t si, uint32_t b,
+                                             const ChunkTable &ct, const RegionArgs &ra, uint32_t *bm) {
     constexpr uint32_t NW = BLOCK / 64, PIECE = 64 * U;
     const uint32_t words = 1u << (g.S - 5);
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint32_t blk = blockIdx.x;
-    const uint32_t si = blk / g.nb, b = blk % g.nb;
-    const ApplySlot A = at.s[si];
     uint32_t *dst = b < g.nb_ldca ? A.ldca + (uint64_t)b * words : A.seav_w + (uint64_t)(b - g.nb_ldca) * words;
     if (A.fresh && b < g.nb_ldca) {
         for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = 0;
@@ -1161,6 +1162,42 @@ __global__ __launch_bounds__(BLOCK) void k_apply_rg(BinGeometry g, ApplyTable at
     }
 }
 
+// One workgroup per (slot, bucket).
+template <int BLOCK, int U>
+__global__ __launch_bounds__(BLOCK) void k_apply_rg(BinGeometry g, ApplyTable at, ChunkTable ct, RegionArgs ra) {
+    extern __shared__ uint32_t bm[];
+    const uint32_t blk = blockIdx.x;
+    const uint32_t si = blk / g.nb, b = blk % g.nb;
+    apply_bucket<BLOCK, U>(g, at.s[si], si, b, ct, ra, bm);
+}
+
+// The same with the router OR merge fused in (Section 4.2): one workgroup per bucket applies the
+// bucket of every slot of the launch in turn and keeps their OR in registers (a 2^S-bit bucket is
+// 32 words per lane of 1024), then writes it to the global sketch's bucket.  The global's previous
+// content is replaced.
+template <int U>
+__global__ __launch_bounds__(1024) void k_apply_rg_merge(BinGeometry g, ApplyTable at, uint32_t n_slots, ChunkTable ct,
+                                                         RegionArgs ra, ApplySlot gs) {
+    extern __shared__ uint32_t bm[];
+    constexpr uint32_t BLOCK = 1024, PER = 32;   // words per lane of a 2^20-bit bucket
+    const uint32_t words = 1u << (g.S - 5);
+    const uint32_t tid = threadIdx.x, b = blockIdx.x;
+    uint32_t acc[PER];
+#pragma unroll
+    for (uint32_t k = 0; k < PER; ++k) acc[k] = 0;
+    for (uint32_t si = 0; si < n_slots; ++si) {
+        apply_bucket<BLOCK, U>(g, at.s[si], si, b, ct, ra, bm);
+#pragma unroll
+        for (uint32_t k = 0; k < PER; ++k)
+            if (k * BLOCK + tid < words) acc[k] |= bm[k * BLOCK + tid];
+        __syncthreads();   // every lane has read bm before the next slot's bucket overwrites it
+    }
+    uint32_t *dst = b < g.nb_ldca ? gs.ldca + (uint64_t)b * words : gs.seav_w + (uint64_t)(b - g.nb_ldca) * words;
+#pragma unroll
+    for (uint32_t k = 0; k < PER; ++k)
+        if (k * BLOCK + tid < words) dst[k * BLOCK + tid] = acc[k];
+}
+
 template <int U>
 static void launch_apply_rg_u(const BinGeometry &g, const ApplyTable &at, const ChunkTable &ct, const RegionArgs &ra,
                               dim3 grid, uint32_t lds, uint32_t block, hipStream_t s, KTiming kt) {
@@ -1188,10 +1225,28 @@ hipError_t launch_apply_rg(const BinGeometry &g, const ApplySlot *slots, uint32_
     return hipGetLastError();
 }
 
+hipError_t launch_apply_rg_merge(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const ChunkTable &ct,
+                                 const RegionArgs &ra, const ApplySlot &global, uint32_t unroll, hipStream_t s,
+                                 KTiming kt) {
+    ApplyTable at{};
+    if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup || ct.n != n_slots || g.S > 20) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
+    const uint32_t lds = (1u << (g.S - 5)) * 4u;
+    const dim3 grid(g.nb), block(1024);
+    switch (unroll) {
+    case 8: hipExtLaunchKernelGGL((k_apply_rg_merge<4>), grid, block, lds, s, kt.start, kt.stop, 0, g, at, n_slots, ct, ra, global); break;
+    case 16: hipExtLaunchKernelGGL((k_apply_rg_merge<8>), grid, block, lds, s, kt.start, kt.stop, 0, g, at, n_slots, ct, ra, global); break;
+    case 32: hipExtLaunchKernelGGL((k_apply_rg_merge<16>), grid, block, lds, s, kt.start, kt.stop, 0, g, at, n_slots, ct, ra, global); break;
+    default: return hipErrorInvalidConfiguration;
+    }
+    return hipGetLastError();
+}
+
 // The spill list (words that did not fit their region), ORed into the sketches with global atomics
 // after the apply phase has written every bucket back.  Normally empty.  The spill counts of
 // consecutive launches alternate between two words: this launch clears the next one's.
-__global__ __launch_bounds__(256) void k_spill(BinGeometry g, ApplyTable at, RegionArgs ra) {
+__global__ __launch_bounds__(256) void k_spill(BinGeometry g, ApplyTable at, RegionArgs ra, ApplySlot gs,
+                                               uint32_t also_global) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *ra.spill_next = 0u;
     __shared__ uint32_t *lp[kMaxGroup];
     __shared__ uint32_t *sp[kMaxGroup];
@@ -1206,20 +1261,24 @@ __global__ __launch_bounds__(256) void k_spill(BinGeometry g, ApplyTable at, Reg
         const uint64_t v = ra.spill_w[i];
         const uint32_t tag = ra.spill_tag[i], si = tag >> 16, b = tag & 0xFFFFu;
         uint32_t *dst = b < g.nb_ldca ? lp[si] + (uint64_t)b * words : sp[si] + (uint64_t)(b - g.nb_ldca) * words;
+        // (with the merge fused into the apply phase, the global sketch gets the word too)
+        uint32_t *gd = b < g.nb_ldca ? gs.ldca + (uint64_t)b * words : gs.seav_w + (uint64_t)(b - g.nb_ldca) * words;
 #pragma unroll
         for (uint32_t f = 0; f < 3; ++f) {
             const uint32_t it = (uint32_t)(v >> (21 * f)) & 0x1FFFFFu;
             global_or(dst + (it >> 5), 1u << (it & 31u));
+            if (also_global) global_or(gd + (it >> 5), 1u << (it & 31u));
         }
     }
 }
 
 hipError_t launch_spill(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const RegionArgs &ra,
-                        hipStream_t s) {
+                        hipStream_t s, const ApplySlot *global) {
     ApplyTable at{};
     if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
     for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
-    hipLaunchKernelGGL(k_spill, dim3(32), dim3(256), 0, s, g, at, ra);   // normally nothing to do
+    const ApplySlot gs = global ? *global : ApplySlot{};
+    hipLaunchKernelGGL(k_spill, dim3(32), dim3(256), 0, s, g, at, ra, gs, global ? 1u : 0u);   // normally nothing to do
     return hipGetLastError();
 }
 

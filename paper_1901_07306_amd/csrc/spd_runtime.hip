@@ -111,6 +111,9 @@ struct spd_ctx {
     uint32_t close_per_cu[3] = {0, 0, 0};   // resident end-of-window workgroups per CU (64, 128, 256 lanes)
     uint32_t spill_parity = 0;       // region layout: which of two spill counts the next launch uses
     CloseBuf cbuf;                  // end-of-window buffers of spd_close_window
+    Slot *merge_into = nullptr;     // spd_scan_batches_merge: the global slot, while its scan runs
+    bool merge_group = false;       // the region launch being enqueued covers the whole merged call
+    bool merged = false;            // the merge was fused into that launch's apply phase
     PendingClose pend[SPD_MAX_PENDING_CLOSES];   // spd_close_begin / spd_close_end
     uint32_t pend_seq = 0;
     uint32_t pend_rec = 0;          // record room a pending close must have (grown after an overflow)
@@ -711,14 +714,26 @@ spd_status region_launch_at(spd_ctx *ctx, const BinGeometry &g, const BatchDesc 
             ctx->bd_next = (ctx->bd_next + 1) % kBdRing;
         }
     }
+    // the router merge fused into the apply phase (1024-lane workgroups hold a bucket's OR in
+    // registers), when this launch covers every router of a merged call
+    const bool fuse = ctx->merge_group && ctx->merge_into && ctx->tune.apply_block == 1024 && g.S <= 20;
+    ApplySlot gas{};
+    if (fuse) {
+        gas.ldca = ctx->merge_into->ldca;
+        gas.seav_w = reinterpret_cast<uint32_t *>(ctx->merge_into->seav);
+    }
     {
         ProfKernel pk(ctx, SPD_K_APPLY);
-        SPD_HIP(ctx, launch_apply_rg(g, as, nsl, ct, ra, ctx->tune.apply_block, ctx->tune.apply_unroll, s, pk.kt));
+        if (fuse)
+            SPD_HIP(ctx, launch_apply_rg_merge(g, as, nsl, ct, ra, gas, ctx->tune.apply_unroll, s, pk.kt));
+        else
+            SPD_HIP(ctx, launch_apply_rg(g, as, nsl, ct, ra, ctx->tune.apply_block, ctx->tune.apply_unroll, s, pk.kt));
     }
     {
         ProfScope ps(ctx, SPD_K_SPILL, s);
-        SPD_HIP(ctx, launch_spill(g, as, nsl, ra, s));
+        SPD_HIP(ctx, launch_spill(g, as, nsl, ra, s, fuse ? &gas : nullptr));
     }
+    if (fuse) ctx->merged = true;
     *rs.parity = par ^ 1u;
     *rs.aux_zero = true;
     return SPD_OK;
@@ -833,6 +848,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
     // launch of each kernel per group, so each slot's buckets are read and written once per group)
     size_t i0 = 0;
     while (i0 < ws.size()) {
+        const size_t group_start = i0;
         std::vector<BatchDesc> bd;
         SlotPtrs sp[kMaxGroup] = {};
         ApplySlot as[kMaxGroup] = {};
@@ -906,7 +922,9 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             const uint32_t chunks = ct.cbase[nsl];
             if (ctx->tune.bin_mode == 2) {
                 // the exact-count layout (less scratch) if the region layout does not fit the budget
+                ctx->merge_group = ctx->merge_into && group_start == 0 && i0 == ws.size();
                 spd_status st = region_launch(ctx, g, bd, tiles, ct, sp, as, seav_clean, nsl, s);
+                ctx->merge_group = false;
                 if (st && st != SPD_E_NOMEM) return st;
                 if (!st) {
                     mark_written(owner, nsl);
@@ -1508,6 +1526,43 @@ spd_status spd_scan_batches(spd_ctx *ctx, const spd_batch *batches, uint32_t n_b
     hipStream_t s = static_cast<hipStream_t>(stream);
     order_stream(ctx, s);
     return scan_work(ctx, ws, s);
+}
+
+spd_status spd_scan_batches_merge(spd_ctx *ctx, const spd_batch *batches, uint32_t n_batches, void *stream) {
+    if (!ctx) return SPD_E_INVALID;
+    if (n_batches && !batches) return fail(ctx, SPD_E_INVALID, "null batch list");
+    std::vector<WorkItem> ws;
+    std::vector<uint32_t> named, fed;
+    for (uint32_t i = 0; i < n_batches; ++i) {
+        spd_status st = validate_batch(ctx, batches[i]);
+        if (st) return st;
+        const uint32_t r = batches[i].router;
+        if (std::find(named.begin(), named.end(), r) == named.end()) named.push_back(r);
+        if (batches[i].n_pairs) {
+            if (std::find(fed.begin(), fed.end(), r) == fed.end()) fed.push_back(r);
+            ws.push_back(WorkItem{&ctx->slots[r], batches[i].pairs_dev, batches[i].n_pairs,
+                                  (batches[i].flags & SPD_BATCH_DST) ? 1u : 0u});
+        }
+    }
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!ws.empty()) {
+        order_stream(ctx, s);
+        // fused only when every named router is scanned here (the others' sketches would be missed)
+        ctx->merge_into = fed.size() == named.size() && !ctx->sliding ? &ctx->slots[ctx->n_routers] : nullptr;
+        ctx->merged = false;
+        spd_status st = scan_work(ctx, ws, s);
+        ctx->merge_into = nullptr;
+        ctx->merge_group = false;
+        if (st) return st;
+        if (ctx->merged) {
+            Slot &g = ctx->slots[ctx->n_routers];
+            g.fresh = false;
+            g.seav_zero = false;
+            return SPD_OK;
+        }
+    }
+    return spd_merge(ctx, named.data(), (uint32_t)named.size(), stream);
 }
 
 spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *stream) {
