@@ -553,7 +553,7 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path.  Several GPUs would each "
+        print("bench.py measures one GPU only: the library has no multi-GPU path.  Several GPUs would each "
               "scan their routers' pairs into their own sketches and OR-combine them once per window.",
               file=sys.stderr)
         return 2
