@@ -50,7 +50,10 @@ def candidate_settings(quick: bool = False) -> List[dict]:
                 dict(bin_mode=2, bucket_bits=20, tile_pairs=4096, bin_block=1024, apply_block=1024, apply_unroll=16),
                 dict(bin_mode=2, bucket_bits=20, tile_pairs=4096, bin_block=512, apply_block=1024, apply_unroll=16),
                 dict(bin_mode=1, bucket_bits=20, tile_pairs=8192, bin_block=1024, apply_block=1024, apply_unroll=16),
-                dict(bin_mode=0, bucket_bits=20, tile_pairs=16384, bin_block=1024, apply_block=1024, apply_unroll=16)]
+                dict(bin_mode=0, bucket_bits=20, tile_pairs=16384, bin_block=1024, apply_block=1024, apply_unroll=16),
+                # small sketches: more, smaller buckets give the apply phase workgroups for every CU
+                dict(bin_mode=2, bucket_bits=17, tile_pairs=4096, bin_block=1024, apply_block=256, apply_unroll=8),
+                dict(bin_mode=2, bucket_bits=18, tile_pairs=4096, bin_block=1024, apply_block=512, apply_unroll=8)]
     out = []
     for mode, S, T, bb, u in itertools.product((0, 1, 2), (19, 20), (8192, 16384), (512, 1024), (8, 16)):
         out.append(dict(bin_mode=mode, bucket_bits=S, tile_pairs=T, bin_block=bb, apply_block=1024, apply_unroll=u))
