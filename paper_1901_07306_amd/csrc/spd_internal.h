@@ -207,10 +207,13 @@ struct RegionArgs {
     uint32_t *spill_next;  // the next launch's count: zeroed by this launch's spill phase
     uint64_t *spill_w;     // [spill_cap] overflow words
     uint32_t *spill_tag;   // [spill_cap] (slot << 16) | bucket of each overflow word
+    uint32_t *ovf_n;       // tiles listed by this launch (zero before the launch)
+    uint32_t *ovf_next;    // the next launch's count: zeroed by this launch's spill phase
+    uint32_t *ovf;         // [ovf_cap] tiles with more sampled pairs than they could stage
     uint64_t chunk_words;  // nb_ldca * capw_l + (nb - nb_ldca) * capw_s
     uint32_t capw_l, capw_s;
     uint32_t spill_cap;    // at least the launch's padded words: the spill list cannot overflow
-    uint32_t pad;
+    uint32_t ovf_cap;      // the launch's tiles: the tile list cannot overflow
 };
 hipError_t launch_clear(const ClearList &clear, hipStream_t s);
 // Region of chunk cc (counted inside slot si) for bucket b: its first word counted from the chunk's
@@ -246,8 +249,9 @@ hipError_t launch_apply_rg(const BinGeometry &g, const ApplySlot *slots, uint32_
 hipError_t launch_apply_rg_merge(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const ChunkTable &ct,
                                  const RegionArgs &ra, const ApplySlot &global, uint32_t unroll, hipStream_t s,
                                  KTiming kt = {});
-hipError_t launch_spill(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const RegionArgs &ra,
-                        hipStream_t s, const ApplySlot *global = nullptr);
+// The spill pass of a region launch over the batches bl (which the listed tiles are read from again).
+hipError_t launch_spill(const Consts &c, const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots,
+                        const RegionArgs &ra, const BatchList &bl, hipStream_t s, const ApplySlot *global = nullptr);
 hipError_t launch_or_merge(uint32_t *dst, const uint32_t *const *src, uint32_t n_src, uint64_t n_words, hipStream_t s);
 hipError_t launch_max_merge_u16(uint16_t *dst, const uint16_t *const *src, uint32_t n_src, uint64_t n_elems,
                                 hipStream_t s);

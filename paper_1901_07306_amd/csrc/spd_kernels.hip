@@ -416,8 +416,9 @@ __device__ void bucket_offsets(uint32_t *cl, uint32_t *cs, uint32_t nb, uint32_t
 }
 
 // Bit addresses of a tile's pairs: LDCA items are counted per bucket in cl (the returned rank is
-// kept per item), sampled pairs are staged in samp (or recorded directly once samp is full).
-template <int LR, int PPT, int BLOCK, bool FULL>
+// kept per item), sampled pairs are staged in samp; once samp is full the rest are recorded directly
+// (DEFER: only counted, the caller hands the whole tile's sampled pairs to a later pass).
+template <int LR, int PPT, int BLOCK, bool FULL, bool DEFER>
 __device__ __forceinline__ void bin_hash_pairs(const Consts &c, const RowLds &rl, const BinGeometry &g, const SlotPtrs &S,
                                                const u32x2 (&pr)[PPT], uint64_t p0, uint64_t n, uint32_t *cl,
                                                uint32_t *samp, uint32_t *misc, uint32_t (&bits)[PPT * LR],
@@ -445,7 +446,7 @@ __device__ __forceinline__ void bin_hash_pairs(const Consts &c, const RowLds &rl
             if (e < g.scap) {
                 samp[2 * e] = hip;
                 samp[2 * e + 1] = b;
-            } else {
+            } else if (!DEFER) {
                 // more sampled pairs than the tile reserved: record them directly
                 uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
                 for (uint32_t r = 0; r < c.sr; ++r) {
@@ -500,9 +501,9 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts c, BinGeometry g, BatchTab
     uint32_t bits[PPT * LR], rk[(PPT * LR + 1) / 2];
     // a full tile (all but the last of a batch) needs no per-pair range test
     if (p0 + (uint64_t)(PPT * BLOCK) <= B.n)
-        bin_hash_pairs<LR, PPT, BLOCK, true>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
+        bin_hash_pairs<LR, PPT, BLOCK, true, false>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
     else
-        bin_hash_pairs<LR, PPT, BLOCK, false>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
+        bin_hash_pairs<LR, PPT, BLOCK, false, false>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
     __syncthreads();
     // a tile with more sampled pairs than it can stage records all of them directly (the decision
     // depends only on the tile's sampled count, so a counting pass can repeat it)
@@ -942,20 +943,17 @@ __global__ __launch_bounds__(BLOCK) void k_region(Consts c, BinGeometry g, Batch
     __syncthreads();
     uint32_t bits[PPT * LR], rk[(PPT * LR + 1) / 2];
     if (full)
-        bin_hash_pairs<LR, PPT, BLOCK, true>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
+        bin_hash_pairs<LR, PPT, BLOCK, true, true>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
     else
-        bin_hash_pairs<LR, PPT, BLOCK, false>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
+        bin_hash_pairs<LR, PPT, BLOCK, false, true>(c, rl, g, S, pr, p0, B.n, cl, samp, misc, bits, rk);
     __syncthreads();
-    // a tile with more sampled pairs than it can stage records all of them directly
+    // a tile with more sampled pairs than it can stage stages none: it is listed, and the spill
+    // pass records all of its sampled pairs once the apply phase has written the buckets
     uint32_t ns = misc[0];
     if (ns > g.scap) {
-        uint32_t *seav_w = reinterpret_cast<uint32_t *>(S.seav);
-        for (uint32_t e = tid; e < g.scap; e += BLOCK) {
-            const uint32_t hip = samp[2 * e], b = samp[2 * e + 1];
-            for (uint32_t r = 0; r < c.sr; ++r) {
-                const uint32_t bit = seav_byte_l(hip, r, rl, c) * 8u + b;
-                global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
-            }
+        if (tid == 0) {
+            const uint32_t k = atomicAdd(ra.ovf_n, 1u);
+            if (k < ra.ovf_cap) ra.ovf[k] = tile;
         }
         ns = 0;
     }
@@ -1104,7 +1102,8 @@ hipError_t launch_clear(const ClearList &clear, hipStream_t s) {
 // Apply phase of the region layout: one workgroup per (slot, bucket) ORs the used part of the
 // bucket's region in each of the slot's chunks into an LDS bitmap.  Work is split into pieces of
 // 64 * U words (one per wavefront at a time); a piece past its region's fill is skipped.
-// Bucket b of slot si: loaded into the LDS bitmap bm (zero for a fresh slot's LDCA bucket), the
+// Bucket b of slot si: loaded into the LDS bitmap bm (zero for a fresh slot: nothing but the
+// spill pass, which runs after this, writes a slot's memory during a launch), the
 // filled part of the bucket's region in every chunk of the slot applied with LDS atomicOr, the
 // region counters read zeroed for the next launch, the bitmap stored back.  Ends with bm complete
 // and visible to the whole workgroup.
@@ -1116,7 +1115,7 @@ __device__ __forceinline__ void apply_bucket(const BinGeometry &g, const ApplySl
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     uint32_t *dst = b < g.nb_ldca ? A.ldca + (uint64_t)b * words : A.seav_w + (uint64_t)(b - g.nb_ldca) * words;
-    if (A.fresh && b < g.nb_ldca) {
+    if (A.fresh) {
         for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = 0;
     } else {
         for (uint32_t w = tid; w < words; w += BLOCK) bm[w] = dst[w];
@@ -1242,14 +1241,21 @@ hipError_t launch_apply_rg_merge(const BinGeometry &g, const ApplySlot *slots, u
     return hipGetLastError();
 }
 
-// The spill list (words that did not fit their region), ORed into the sketches with global atomics
-// after the apply phase has written every bucket back.  Normally empty.  The spill counts of
-// consecutive launches alternate between two words: this launch clears the next one's.
-__global__ __launch_bounds__(256) void k_spill(BinGeometry g, ApplyTable at, RegionArgs ra, ApplySlot gs,
-                                               uint32_t also_global) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *ra.spill_next = 0u;
+// The spill pass, once the apply phase has written every bucket back (normally nothing to do): the
+// words that did not fit their region, and the sampled pairs of the tiles the binning kernel listed
+// (more than a tile could stage), re-read from the batch; both recorded with global atomics.  The
+// counts of consecutive launches alternate between two words each: this launch clears the next
+// one's.
+__global__ __launch_bounds__(256) void k_spill(Consts c, BinGeometry g, ApplyTable at, RegionArgs ra, ApplySlot gs,
+                                               uint32_t also_global, BatchList bl) {
+    __shared__ RowLds rl;
     __shared__ uint32_t *lp[kMaxGroup];
     __shared__ uint32_t *sp[kMaxGroup];
+    rows_to_lds(rl, c);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *ra.spill_next = 0u;
+        *ra.ovf_next = 0u;
+    }
     if (threadIdx.x < (uint32_t)kMaxGroup) {
         lp[threadIdx.x] = at.s[threadIdx.x].ldca;
         sp[threadIdx.x] = at.s[threadIdx.x].seav_w;
@@ -1270,15 +1276,35 @@ __global__ __launch_bounds__(256) void k_spill(BinGeometry g, ApplyTable at, Reg
             if (also_global) global_or(gd + (it >> 5), 1u << (it & 31u));
         }
     }
+    // listed tiles, one workgroup per tile at a time
+    const uint32_t t0 = *ra.ovf_n, nt = t0 < ra.ovf_cap ? t0 : ra.ovf_cap;
+    for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const uint32_t tile = ra.ovf[t];
+        const BatchDesc B = batch_of(bl, tile);
+        const uint64_t p0 = (uint64_t)(tile - B.first_tile) * g.tile_pairs;
+        const uint64_t p1 = p0 + g.tile_pairs < B.n ? p0 + g.tile_pairs : B.n;
+        const u32x2 *pairs = reinterpret_cast<const u32x2 *>(B.pairs);
+        uint32_t *seav_w = sp[B.slot];
+        for (uint64_t i = p0 + threadIdx.x; i < p1; i += 256) {
+            const u32x2 pr = load_pair(pairs, i, B.swap);
+            if (!sampled(pr.y, c)) continue;
+            const uint32_t b = se_bit(pr.y, c);
+            for (uint32_t r = 0; r < c.sr; ++r) {
+                const uint32_t bit = seav_byte_l(pr.x, r, rl, c) * 8u + b;
+                global_or(seav_w + (bit >> 5), 1u << (bit & 31u));
+                if (also_global) global_or(gs.seav_w + (bit >> 5), 1u << (bit & 31u));
+            }
+        }
+    }
 }
 
-hipError_t launch_spill(const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots, const RegionArgs &ra,
-                        hipStream_t s, const ApplySlot *global) {
+hipError_t launch_spill(const Consts &c, const BinGeometry &g, const ApplySlot *slots, uint32_t n_slots,
+                        const RegionArgs &ra, const BatchList &bl, hipStream_t s, const ApplySlot *global) {
     ApplyTable at{};
     if (n_slots == 0 || n_slots > (uint32_t)kMaxGroup) return hipErrorInvalidValue;
     for (uint32_t i = 0; i < n_slots; ++i) at.s[i] = slots[i];
     const ApplySlot gs = global ? *global : ApplySlot{};
-    hipLaunchKernelGGL(k_spill, dim3(32), dim3(256), 0, s, g, at, ra, gs, global ? 1u : 0u);   // normally nothing to do
+    hipLaunchKernelGGL(k_spill, dim3(32), dim3(256), 0, s, c, g, at, ra, gs, global ? 1u : 0u, bl);   // normally nothing to do
     return hipGetLastError();
 }
 

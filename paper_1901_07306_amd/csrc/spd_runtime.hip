@@ -27,7 +27,6 @@ struct Slot {
     uint8_t *ldca_at = nullptr;  // AT pool: one 8-bit counter per bit
     uint8_t *seav_at = nullptr;
     bool fresh = true;           // logically all zero; device memory not yet cleared
-    bool seav_zero = false;      // fresh, and its SEAV already zeroed (after the close that reset it)
 };
 
 struct WorkItem {
@@ -422,12 +421,12 @@ spd_status clear_slot(spd_ctx *ctx, Slot &s, hipStream_t st) {
         SPD_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(s.mem), slot_words(ctx), empty_fill(ctx), st));
     }
     s.fresh = false;
-    s.seav_zero = false;
     return SPD_OK;
 }
 
-// Zero only the SEAV of a fresh slot: the binned scan rewrites every LDCA bucket of a fresh slot
-// from zero, while its SEAV buckets are read back (they may hold bits recorded directly).
+// Zero only the SEAV of a fresh slot: the per-tile and exact-count layouts rewrite every LDCA bucket
+// of a fresh slot from zero, while its SEAV buckets are read back (they may hold bits recorded
+// directly).
 spd_status clear_seav(spd_ctx *ctx, Slot &s, hipStream_t st) {
     ProfScope ps(ctx, SPD_K_FILL, st);
     SPD_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(s.seav), ctx->seav_alloc / 4, 0u, st));
@@ -558,8 +557,8 @@ static uint32_t region_cap(const spd_ctx *ctx, double e_tile, double t) {
 }
 
 // The region layout of one launch over the slots of ct (pointers left null): items_words = 32-bit
-// words of the regions, the spill words and the spill tags; cur_words = two spill counts, two spare
-// words and the region counters, a multiple of 4.
+// words of the regions, the spill words, the spill tags and the tile list; cur_words = two spill
+// counts, two tile-list counts and the region counters, a multiple of 4.
 void region_layout(const spd_ctx *ctx, const BinGeometry &g, const ChunkTable &ct, uint64_t tiles, RegionArgs *ra,
                    uint64_t *items_words, uint64_t *cur_words) {
     double el, es;
@@ -578,9 +577,11 @@ void region_layout(const spd_ctx *ctx, const BinGeometry &g, const ChunkTable &c
         ra->caps_last[k] = rem ? region_cap(ctx, es, rem) : ra->capw_s;
         words += ra->full[k] * ra->chunk_words + (rem ? g.nb_ldca * ra->capl_last[k] + nbs * ra->caps_last[k] : 0);
     }
-    // every padded word of the launch fits the spill list: at most cap / 3 words per tile
+    // every padded word of the launch fits the spill list: at most cap / 3 words per tile; every
+    // tile fits the tile list
     ra->spill_cap = (uint32_t)std::min<uint64_t>(tiles * g.cap / 3, 0xFFFFFFFFull);
-    *items_words = words * 2 + (uint64_t)ra->spill_cap * 3;
+    ra->ovf_cap = (uint32_t)tiles;
+    *items_words = words * 2 + (uint64_t)ra->spill_cap * 3 + tiles;
     *cur_words = (4 + (uint64_t)ct.cbase[ct.n] * g.nb + 3) / 4 * 4;
 }
 
@@ -605,7 +606,7 @@ void region_bound(const spd_ctx *ctx, const BinGeometry &g, uint64_t tiles, uint
         words = (double)(tiles / kChunk) * chunk_words + A * R + B * std::sqrt(kMaxGroup * R) + kMaxGroup * C;
     }
     const uint64_t spill = std::min<uint64_t>(tiles * g.cap / 3, 0xFFFFFFFFull);
-    *items_words = (uint64_t)std::ceil(words) * 2 + spill * 3;
+    *items_words = (uint64_t)std::ceil(words) * 2 + spill * 3 + tiles;
     *cur_words = (4 + (tiles / kChunk + kMaxGroup) * g.nb + 3) / 4 * 4;
 }
 
@@ -654,25 +655,30 @@ struct RegionScratch {
     uint32_t *parity;
 };
 
-// One group of the region layout in the given scratch: clear (fresh SEAVs, region counters), bin
-// into the regions, apply every (slot, bucket), then the spill list.  SPD_E_INVALID (nothing
-// enqueued) if the group's layout does not fit the scratch.
+// One group of the region layout in the given scratch: clear the counters (unless known zero), bin
+// into the regions, apply every (slot, bucket), then the spill pass.  A fresh slot needs no clear:
+// the apply phase writes all of its buckets from zero, and only the spill pass, after it, writes
+// the slot directly.  SPD_E_INVALID (nothing enqueued) if the group's layout does not fit the
+// scratch.
 spd_status region_launch_at(spd_ctx *ctx, const BinGeometry &g, const BatchDesc *bd, uint32_t nbd, uint32_t tiles,
-                            const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, const bool *seav_clean,
-                            uint32_t nsl, const RegionScratch &rs, hipStream_t s) {
+                            const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, uint32_t nsl,
+                            const RegionScratch &rs, hipStream_t s) {
     RegionArgs ra{};
     uint64_t items_words = 0, cur_words = 0;
     region_layout(ctx, g, ct, tiles, &ra, &items_words, &cur_words);
     if (ra.chunk_words >= (1ull << 31)) return fail(ctx, SPD_E_INVALID, "region layout: chunk too large");
     if (items_words > rs.items_words || cur_words > rs.aux_words)
         return fail(ctx, SPD_E_INVALID, "region layout larger than its scratch");
-    const uint64_t region_words = items_words - (uint64_t)ra.spill_cap * 3;   // 32-bit words
+    const uint64_t region_words = items_words - (uint64_t)ra.spill_cap * 3 - ra.ovf_cap;   // 32-bit words
     const uint32_t par = *rs.parity;
     ra.items = reinterpret_cast<uint64_t *>(rs.items);
     ra.spill_w = reinterpret_cast<uint64_t *>(rs.items + region_words);
     ra.spill_tag = rs.items + region_words + (uint64_t)ra.spill_cap * 2;
+    ra.ovf = rs.items + region_words + (uint64_t)ra.spill_cap * 3;
     ra.spill_n = rs.aux + par;
     ra.spill_next = rs.aux + (par ^ 1u);
+    ra.ovf_n = rs.aux + 2 + par;
+    ra.ovf_next = rs.aux + 2 + (par ^ 1u);
     ra.cur = rs.aux + 4;
     // a few batches travel in the kernel arguments; more go through the pinned staging ring
     BatchList bl{};
@@ -686,33 +692,17 @@ spd_status region_launch_at(spd_ctx *ctx, const BinGeometry &g, const BatchDesc 
         if (st) return st;
         bl.b = bdev;
     }
-    {
+    if (!*rs.aux_zero) {   // after (re)allocation, another layout's use, or a failed launch
         ProfScope ps(ctx, SPD_K_FILL, s);
         ClearList cl{};
-        if (!*rs.aux_zero) {   // after (re)allocation, another layout's use, or a failed launch
-            cl.p[cl.n] = rs.aux;
-            cl.words[cl.n++] = rs.aux_words;
-        }
-        for (uint32_t k = 0; k < nsl; ++k) {
-            if (!as[k].fresh || seav_clean[k]) continue;
-            if (cl.n == (uint32_t)kMaxGroup) {
-                SPD_HIP(ctx, launch_clear(cl, s));
-                cl.n = 0;
-            }
-            cl.p[cl.n] = as[k].seav_w;
-            cl.words[cl.n++] = ctx->seav_alloc / 4;
-        }
+        cl.p[cl.n] = rs.aux;
+        cl.words[cl.n++] = rs.aux_words;
         SPD_HIP(ctx, launch_clear(cl, s));
     }
     *rs.aux_zero = false;   // until the launch's apply and spill phases are enqueued
     {
         ProfKernel pk(ctx, SPD_K_BIN);
         SPD_HIP(ctx, launch_region(ctx->c, g, bl, tiles, ct, sp, ra, s, pk.kt));
-        if (!inl) {
-            // the staging slot may be rewritten once the binning kernel has read it
-            SPD_HIP(ctx, hipEventRecord(ctx->bd_ev[ctx->bd_next], s));
-            ctx->bd_next = (ctx->bd_next + 1) % kBdRing;
-        }
     }
     // the router merge fused into the apply phase (1024-lane workgroups hold a bucket's OR in
     // registers), when this launch covers every router of a merged call
@@ -731,7 +721,12 @@ spd_status region_launch_at(spd_ctx *ctx, const BinGeometry &g, const BatchDesc 
     }
     {
         ProfScope ps(ctx, SPD_K_SPILL, s);
-        SPD_HIP(ctx, launch_spill(g, as, nsl, ra, s, fuse ? &gas : nullptr));
+        SPD_HIP(ctx, launch_spill(ctx->c, g, as, nsl, ra, bl, s, fuse ? &gas : nullptr));
+        if (!inl) {
+            // the staging slot may be rewritten once the spill pass (the last reader) has read it
+            SPD_HIP(ctx, hipEventRecord(ctx->bd_ev[ctx->bd_next], s));
+            ctx->bd_next = (ctx->bd_next + 1) % kBdRing;
+        }
     }
     if (fuse) ctx->merged = true;
     *rs.parity = par ^ 1u;
@@ -742,8 +737,7 @@ spd_status region_launch_at(spd_ctx *ctx, const BinGeometry &g, const BatchDesc 
 // The same in the context's scratch, grown on demand within the HBM budget: SPD_E_NOMEM (nothing
 // enqueued) if it does not fit.
 spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<BatchDesc> &bd, uint32_t tiles,
-                         const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, const bool *seav_clean,
-                         uint32_t nsl, hipStream_t s) {
+                         const ChunkTable &ct, const SlotPtrs *sp, const ApplySlot *as, uint32_t nsl, hipStream_t s) {
     RegionArgs ra{};
     uint64_t items_words = 0, cur_words = 0;
     region_layout(ctx, g, ct, tiles, &ra, &items_words, &cur_words);
@@ -752,7 +746,7 @@ spd_status region_launch(spd_ctx *ctx, const BinGeometry &g, const std::vector<B
     if (!st) st = ensure_aux(ctx, cur_words, s);
     if (st) return st;
     const RegionScratch rs{ctx->items, ctx->items_words, ctx->aux, ctx->aux_words, &ctx->aux_zero, &ctx->spill_parity};
-    return region_launch_at(ctx, g, bd.data(), (uint32_t)bd.size(), tiles, ct, sp, as, seav_clean, nsl, rs, s);
+    return region_launch_at(ctx, g, bd.data(), (uint32_t)bd.size(), tiles, ct, sp, as, nsl, rs, s);
 }
 
 // Record batches into slots.  Batches of one slot are kept together so that each slot's tiles are
@@ -818,15 +812,12 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
     }
     // Binned: a slot's flags change only once a group covering it has been enqueued, so that an
     // error return (a budget refusal before anything was enqueued) leaves every slot as it was.
-    // A fresh slot's LDCA buckets are written from zero by the apply phase; its SEAV is cleared
-    // inside the scan (the clear kernel, the counting kernel, or a fill before the per-tile
-    // binning), unless the close that reset it has already zeroed it (seav_zero).
+    // A fresh slot's buckets are written from zero by the apply phase of the region layout; the
+    // other two layouts do so for its LDCA buckets and clear its SEAV inside the scan (the counting
+    // kernel, or a fill before the per-tile binning).
     // later groups of the same call OR into the slots an enqueued group has written
     auto mark_written = [](Slot *const *owner, uint32_t n) {
-        for (uint32_t k = 0; k < n; ++k) {
-            owner[k]->fresh = false;
-            owner[k]->seav_zero = false;
-        }
+        for (uint32_t k = 0; k < n; ++k) owner[k]->fresh = false;
     };
     // split batches larger than one launch may take: launch_pairs, and for the region and
     // exact-count layouts the 32-bit item offsets of one launch (tiles * cap < 2^32)
@@ -852,7 +843,6 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
         std::vector<BatchDesc> bd;
         SlotPtrs sp[kMaxGroup] = {};
         ApplySlot as[kMaxGroup] = {};
-        bool seav_clean[kMaxGroup] = {};   // fresh slots whose SEAV is already zero
         Slot *owner[kMaxGroup] = {};
         uint32_t nsl = 0, tiles = 0;
         uint64_t lpairs = 0;
@@ -871,9 +861,8 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
                 as[nsl].ldca = w.slot->ldca;
                 as[nsl].seav_w = reinterpret_cast<uint32_t *>(w.slot->seav);
                 as[nsl].tile_lo = tiles;
-                // a fresh slot's LDCA buckets are written from zero by this launch
+                // a fresh slot's buckets are written from zero by this launch
                 as[nsl].fresh = w.slot->fresh ? 1u : 0u;
-                seav_clean[nsl] = w.slot->fresh && w.slot->seav_zero;
                 owner[nsl] = w.slot;
                 ++nsl;
             }
@@ -891,7 +880,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             spd_status st = ensure_scratch(ctx, items_words, meta_words, s);
             if (st) return st;
             for (uint32_t k = 0; k < nsl; ++k)   // SEAV bits may be recorded directly by the binning
-                if (as[k].fresh && !seav_clean[k]) {
+                if (as[k].fresh) {
                     st = clear_seav(ctx, *owner[k], s);
                     if (st) return st;
                 }
@@ -923,7 +912,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             if (ctx->tune.bin_mode == 2) {
                 // the exact-count layout (less scratch) if the region layout does not fit the budget
                 ctx->merge_group = ctx->merge_into && group_start == 0 && i0 == ws.size();
-                spd_status st = region_launch(ctx, g, bd, tiles, ct, sp, as, seav_clean, nsl, s);
+                spd_status st = region_launch(ctx, g, bd, tiles, ct, sp, as, nsl, s);
                 ctx->merge_group = false;
                 if (st && st != SPD_E_NOMEM) return st;
                 if (!st) {
@@ -943,7 +932,7 @@ spd_status scan_work(spd_ctx *ctx, std::vector<WorkItem> &ws, hipStream_t s) {
             if (st) return st;
             ClearList cl{};
             for (uint32_t k = 0; k < nsl; ++k)
-                if (as[k].fresh && !seav_clean[k]) {
+                if (as[k].fresh) {
                     cl.p[cl.n] = as[k].seav_w;
                     cl.words[cl.n++] = ctx->seav_alloc / 4;
                 }
@@ -1045,14 +1034,11 @@ spd_status scan_noalloc(spd_ctx *ctx, Slot *sl, const uint32_t *pairs, uint64_t 
         const BatchDesc bd{pairs + 2 * off, cn, 0, 0, swap, 0};
         SlotPtrs sp[kMaxGroup] = {};
         ApplySlot as[kMaxGroup] = {};
-        bool clean[kMaxGroup] = {};
         sp[0] = ptrs_of(*sl);
         as[0] = ApplySlot{sl->ldca, reinterpret_cast<uint32_t *>(sl->seav), 0, tiles, sl->fresh ? 1u : 0u, 0};
-        clean[0] = sl->fresh && sl->seav_zero;
-        spd_status st = region_launch_at(ctx, g, &bd, 1, tiles, ct, sp, as, clean, 1, rs, s);
+        spd_status st = region_launch_at(ctx, g, &bd, 1, tiles, ct, sp, as, 1, rs, s);
         if (st) return st;
         sl->fresh = false;
-        sl->seav_zero = false;
         ctx->stats.binned_launches++;
     }
     ctx->stats.pairs_scanned += n;
@@ -1558,7 +1544,6 @@ spd_status spd_scan_batches_merge(spd_ctx *ctx, const spd_batch *batches, uint32
         if (ctx->merged) {
             Slot &g = ctx->slots[ctx->n_routers];
             g.fresh = false;
-            g.seav_zero = false;
             return SPD_OK;
         }
     }
@@ -1583,7 +1568,6 @@ spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *st
     if (live.empty()) {
         if (ctx->sliding) return clear_slot(ctx, g, s);
         g.fresh = true;
-        g.seav_zero = false;
         return SPD_OK;
     }
     const uint64_t words = slot_words(ctx);
@@ -1609,7 +1593,6 @@ spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *st
         }
     }
     g.fresh = false;
-    g.seav_zero = false;
     return SPD_OK;
 }
 
@@ -1629,13 +1612,6 @@ spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_ho
     SPD_HIP(ctx, hipStreamSynchronize(s));
     st = close_finish(ctx, *sl, ctx->cbuf, s, &res);
     if (st) return st;
-    if (!ctx->sliding && !ctx->cbuf.empty) {
-        // the window is reported (no re-run can need it): zero its SEAV now, while the host builds
-        // the report and submits the next scan, instead of at the start of that scan
-        ProfScope ps(ctx, SPD_K_FILL, s);
-        SPD_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sl->seav), ctx->seav_alloc / 4, 0u, s));
-        sl->seav_zero = true;
-    }
     const uint32_t n = (uint32_t)res.size();
     const uint32_t w = std::min(n, cap);
     if (w) std::memcpy(out_host, res.data(), (size_t)w * sizeof(spd_superpoint));
@@ -1671,15 +1647,7 @@ spd_status spd_close_begin(spd_ctx *ctx, int32_t target, void *stream, uint32_t 
     order_stream(ctx, s);
     spd_status st = close_launch(ctx, *sl, pc.cb, s);
     if (st) return st;
-    if (!ctx->sliding) {
-        if (!pc.cb.empty) {
-            // the next window's scans, enqueued after this, start from a zero SEAV
-            ProfScope ps(ctx, SPD_K_FILL, s);
-            SPD_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sl->seav), ctx->seav_alloc / 4, 0u, s));
-            sl->seav_zero = true;
-        }
-        sl->fresh = true;
-    }
+    if (!ctx->sliding) sl->fresh = true;   // the next window's scans, enqueued after this, start from zero
     SPD_HIP(ctx, hipEventRecord(pc.done, s));
     pc.busy = true;
     pc.seq = (++ctx->pend_seq) & 0x0FFFFFFFu;
@@ -1731,7 +1699,6 @@ spd_status spd_reset(spd_ctx *ctx, int32_t target, void *stream) {
     order_stream(ctx, s);
     if (ctx->sliding) return clear_slot(ctx, *sl, s);
     sl->fresh = true;   // the next scan starts the slot from zero
-    sl->seav_zero = false;
     return SPD_OK;
 }
 

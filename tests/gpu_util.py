@@ -83,3 +83,32 @@ def oracle_sketch_threads(mp, parts, threads=8):
     for s in sks[1:]:
         out.merge(s)
     return out
+
+
+def sampled_oips(mp, n, rng):
+    """n distinct destinations that the sampling of Section 3.1 keeps for parameters mp: the low tau
+    bits of H1(oip) zero (tau from Eq. 1), found with the oracle's hash."""
+    mul, add = mp.hashes()
+    mask = (1 << oracle.tau(mp.theta)) - 1
+    out = set()
+    while len(out) < n:
+        for x in rng.integers(0, 1 << 32, size=2 * (n - len(out)) + 16, dtype=np.uint64).tolist():
+            if oracle.hash32(x, mul[0], add[0], 32) & mask == 0:
+                out.add(x)
+    return np.array(sorted(out)[:n], np.uint32)
+
+
+def overflow_traffic(mp, rng, n_hosts, peers, noise):
+    """Pairs with a contiguous run of n_hosts * peers pairs whose destinations are all sampled
+    (n_hosts hosts with `peers` distinct sampled peers each, shuffled within the run), between two
+    halves of `noise` random pairs.  With tau >= 1 every binning tile inside the run has more
+    sampled pairs than it stages (about half its pairs, plus a margin).  Returns (pairs, hosts)."""
+    pool = sampled_oips(mp, max(4 * peers, 4096), rng)
+    hosts = st.distinct_ips(rng, n_hosts)
+    run = np.concatenate([np.stack([np.full(peers, h, np.uint32),
+                                    pool[rng.choice(pool.size, size=peers, replace=False)]], axis=1)
+                          for h in hosts])
+    run = run[rng.permutation(len(run))]
+    a = random_pairs(rng, noise // 2)
+    b = random_pairs(rng, noise - noise // 2)
+    return np.concatenate([a, run, b]), hosts

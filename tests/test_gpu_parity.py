@@ -14,8 +14,8 @@ import pytest
 
 import oracle
 import synth_traffic as st
-from gpu_util import (assert_same_report, assert_same_sketch, heavy_hosts, log, oracle_sketch, random_pairs,
-                      set_tuning, to_dev)
+from gpu_util import (assert_same_report, assert_same_sketch, heavy_hosts, log, oracle_sketch, overflow_traffic,
+                      random_pairs, set_tuning, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -369,12 +369,14 @@ def test_plain_64m_full_window():
             det.close()
 
 
-def test_bucket_major_overflow_tile_records_seav_directly():
-    """A tile whose sampled pairs exceed its LDS reservation records its SEAV bits directly; the
-    counting pass must leave them out consistently (bucket-major layout)."""
-    mp = st.CONFIGS["plain_64m"].params.replace(theta=8)    # tau = 0: every pair is sampled
+def test_overflow_tiles_every_layout():
+    """Tiles with more sampled pairs than they stage (a run of pairs whose destinations are all
+    sampled, tau = 1): the per-tile and exact-count layouts record their SEAV bits directly (the
+    counting pass must leave them out consistently), the region layout lists the tiles for its
+    spill pass."""
+    mp = st.CONFIGS["plain_64m"].params.replace(theta=16)   # tau = 1: about half the pairs sampled
     rng = np.random.default_rng(71)
-    pairs, _ = heavy_hosts(rng, 40, 1200, noise=30_000)
+    pairs, _ = overflow_traffic(mp, rng, 12, 2500, noise=30_000)
     for tune in (BUCKET_MAJOR, BUCKET_MAJOR_SMALL, BINNED_TILES, REGION, REGION_SMALL):
         det = detector(mp, **tune)
         try:
