@@ -16,9 +16,9 @@
  *    (element 0 = hip, the monitored host; element 1 = oip, its opposite IP), 8-byte aligned.
  *    They must stay valid until the stream has passed the scan.
  *  - Streams are hipStream_t values passed as void* (NULL = the null stream).  Scans, merges
- *    and slides are asynchronous on that stream.  Close waits for its stream, builds the report
- *    and, in discrete mode, enqueues the reset of the closed window on that stream before it
- *    returns (so the reset overlaps the caller's next steps); export and import synchronise.
+ *    and slides are asynchronous on that stream.  Close waits for its stream and builds the
+ *    report; in discrete mode the closed window's reset needs no device work (the next scan
+ *    writes the sketch from zero); export and import synchronise.
  *    Calls on one context are ordered among themselves whatever streams they name: the library
  *    makes each call's stream wait for the previous call's work.
  *  - The library owns all sketch state, in device memory of the device that was current at
@@ -218,8 +218,8 @@ spd_status spd_merge(spd_ctx *ctx, const uint32_t *routers, uint32_t n, void *st
  * (Section 3.2, Eq. 3), keep those whose ULDC estimate reaches theta (Section 3.3, Eq. 4), and
  * write them to out_host (host memory) sorted by ip ascending.  *n_out = number of super points;
  * if it exceeds cap the first cap are written and SPD_E_TRUNCATED is returned.
- * Discrete mode: the target's sketch is then reset to zero (a new window starts); the reset is
- * enqueued on `stream` and may still run when the call returns (later calls are ordered after it).
+ * Discrete mode: the target's sketch is then reset to zero (a new window starts; no device work:
+ * its next scan writes the sketch from zero).
  * Sliding mode: reports the window of the last K slices; nothing is reset. */
 spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_host, uint32_t cap,
                             uint32_t *n_out, void *stream);
