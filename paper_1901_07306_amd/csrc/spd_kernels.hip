@@ -2046,18 +2046,26 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
 // After k_close (the launch boundary orders every workgroup's records before this): the counts
 // and the first records go to host-visible memory, so that no copy follows, and the counters are
 // zeroed for the next launch.  One workgroup.
+// Last of all it writes the close's sequence number (counters[2] + 1, kept in counters[2]) to the
+// host, after a system-scope fence, so that the host may poll that word instead of waiting for the
+// stream.
 __global__ __launch_bounds__(256) void k_close_out(CloseArgs a) {
     const uint32_t n = a.counters[0], cand = a.counters[1];
     const uint32_t m = min(min(n, a.rec_cap), a.host_recs);
     const uint2 *src = reinterpret_cast<const uint2 *>(a.rec);
     uint2 *dst = reinterpret_cast<uint2 *>(a.host_out + 4);
     for (uint32_t i = threadIdx.x; i < m; i += 256) dst[i] = src[i];
+    __threadfence_system();   // this thread's records reach the host before the sequence number
     __syncthreads();
     if (threadIdx.x == 0) {
+        const uint32_t seq = a.counters[2] + 1u;
         a.host_out[0] = n;
         a.host_out[1] = cand;
         a.counters[0] = 0u;
         a.counters[1] = 0u;
+        a.counters[2] = seq;
+        __threadfence_system();
+        __hip_atomic_store(a.host_out + 2, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

@@ -1,6 +1,8 @@
 // Host runtime of libspd: parameter derivation, contexts, router slots, scratch memory, kernel
 // dispatch and the C ABI declared in include/spd.h.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -41,9 +43,10 @@ constexpr uint32_t kRecChunk = 4096;   // records copied back together with the 
 
 // Device and pinned host buffers of one end-of-window pass.
 struct CloseBuf {
-    // one device buffer: 4 counters ([0] reported, [1] candidates; zero between launches) then the
-    // (ip, z0) records.  The end-of-window launch itself copies the counters and the first
-    // kRecChunk records to h_counters.
+    // one device buffer: 4 counters ([0] reported, [1] candidates, both zero between launches;
+    // [2] the sequence number of the last close) then the (ip, z0) records.  The end-of-window
+    // launch itself copies the counters and the first kRecChunk records to h_counters, and the
+    // sequence number last.
     uint32_t *counters = nullptr;
     uint32_t *rec = nullptr;          // counters + 4
     uint32_t rec_cap = 0;
@@ -53,6 +56,7 @@ struct CloseBuf {
     uint32_t *h_rec = nullptr;        // pinned, all records when there are more than kRecChunk
     uint32_t h_rec_cap = 0;
     bool empty = false;               // the slot was fresh: nothing was launched
+    uint32_t seq = 0;                 // the sequence number the last enqueued close will write
     hipGraphExec_t graph = nullptr;   // captured close of graph_slot
     const Slot *graph_slot = nullptr;
     const uint32_t *graph_rec = nullptr;
@@ -1055,6 +1059,8 @@ spd_status close_rec_alloc(spd_ctx *ctx, CloseBuf &cb, uint32_t cap) {
     SPD_HIP(ctx, hipMemset(cb.counters, 0, 16));   // once; each launch leaves them zero
     cb.rec = cb.counters + 4;
     cb.rec_cap = cap;
+    cb.seq = 0;   // (no close of this buffer is in flight)
+    if (cb.h_counters) cb.h_counters[2] = 0;
     return SPD_OK;
 }
 
@@ -1070,6 +1076,7 @@ spd_status close_buf_init(spd_ctx *ctx, CloseBuf &cb) {
     if (!cb.h_counters) {
         SPD_HIP(ctx, hipHostMalloc((void **)&cb.h_counters, 16 + (uint64_t)kRecChunk * 8, hipHostMallocMapped));
         SPD_HIP(ctx, hipHostGetDevicePointer((void **)&cb.d_counters, cb.h_counters, 0));
+        std::memset(cb.h_counters, 0, 16);
     }
     return SPD_OK;
 }
@@ -1152,6 +1159,27 @@ spd_status close_launch_ops(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStrea
     else if (ctx->sliding)
         SPD_HIP(ctx, launch_bit_view(sl.seav_ts, ctx->seav_alloc * 8, (uint16_t)a.thr, reinterpret_cast<uint32_t *>(cb.seav_bits), s));
     SPD_HIP(ctx, launch_close(ctx->c, a, close_mode(ctx), block, grid, s));
+    ++cb.seq;
+    return SPD_OK;
+}
+
+// Waits for the close last enqueued on cb: polls the sequence number that its last kernel writes
+// to mapped host memory (no interrupt and no sleep between the kernel's end and the report), and
+// past kCloseSpinMs waits for `ev` (or the stream) instead, which also reports a failed launch.
+constexpr int kCloseSpinMs = 20;
+spd_status close_wait(spd_ctx *ctx, const CloseBuf &cb, hipStream_t s, hipEvent_t ev = nullptr) {
+    const volatile uint32_t *flag = cb.h_counters + 2;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t it = 1;; ++it) {
+        if (*flag == cb.seq) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return SPD_OK;
+        }
+        if ((it & 255u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(kCloseSpinMs)) break;
+        __builtin_ia32_pause();
+    }
+    if (ev) SPD_HIP(ctx, hipEventSynchronize(ev));
+    else SPD_HIP(ctx, hipStreamSynchronize(s));
     return SPD_OK;
 }
 
@@ -1175,9 +1203,11 @@ spd_status close_launch_graph(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStr
         hipGraph_t g = nullptr;
         const bool prof = ctx->prof_on;
         ctx->prof_on = false;   // no event nodes inside the graph
+        const uint32_t seq = cb.seq;   // (capture runs nothing)
         SPD_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         spd_status cst = close_launch_ops(ctx, sl, cb, s);
         hipError_t e = hipStreamEndCapture(s, &g);
+        cb.seq = seq;
         ctx->prof_on = prof;
         if (cst) {
             if (g) (void)hipGraphDestroy(g);
@@ -1192,6 +1222,7 @@ spd_status close_launch_graph(spd_ctx *ctx, const Slot &sl, CloseBuf &cb, hipStr
     }
     ProfScope ps(ctx, SPD_K_CLOSE, s);
     SPD_HIP(ctx, hipGraphLaunch(cb.graph, s));
+    ++cb.seq;
     return SPD_OK;
 }
 
@@ -1609,7 +1640,10 @@ spd_status spd_close_window(spd_ctx *ctx, int32_t target, spd_superpoint *out_ho
     std::vector<spd_superpoint> res;
     spd_status st = close_launch(ctx, *sl, ctx->cbuf, s);
     if (st) return st;
-    SPD_HIP(ctx, hipStreamSynchronize(s));
+    if (!ctx->cbuf.empty) {
+        st = close_wait(ctx, ctx->cbuf, s);
+        if (st) return st;
+    }
     st = close_finish(ctx, *sl, ctx->cbuf, s, &res);
     if (st) return st;
     const uint32_t n = (uint32_t)res.size();
@@ -1665,7 +1699,12 @@ spd_status spd_close_end(spd_ctx *ctx, uint32_t ticket, spd_superpoint *out_host
     DeviceGuard dg(ctx->device);
     PendingClose &pc = ctx->pend[i];
     pc.busy = false;   // the ticket is spent whatever follows
-    SPD_HIP(ctx, hipEventSynchronize(pc.done));
+    {
+        // (a later call's work on this close's buffers is ordered after it by order_stream)
+        spd_status st = pc.cb.empty ? SPD_OK : close_wait(ctx, pc.cb, nullptr, pc.done);
+        if (!st && pc.cb.empty) SPD_HIP(ctx, hipEventSynchronize(pc.done));
+        if (st) return st;
+    }
     ctx->stats.closes++;
     std::vector<spd_superpoint> res;
     if (pc.cb.empty) {
