@@ -1902,18 +1902,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     for (uint64_t wi = (uint64_t)blockIdx.x * NW + wid; wi < n_items; wi += (uint64_t)gridDim.x * NW) {
         const uint32_t rp = (uint32_t)(wi >> a.parts_log2), part = (uint32_t)wi & part_mask;
         const uint64_t sea = (uint64_t)rp * c.sea_bytes;
-        // stage the whole SEA in LDS (when it fits), eight loads in flight per lane
+        // stage the whole SEA in LDS (when it fits) with 32-bit loads, up to eight in flight per lane
+        // (an SEA is a whole number of words, rows of 2^IBN >= 4 bytes, and so is its offset)
         auto se_at = [&](uint32_t byte) -> uint32_t { return staged ? sea8[byte] : load_se<MODE>(a, sea + byte); };
-        for (uint32_t b0 = 0; staged && b0 < c.sea_bytes; b0 += 64 * 8) {
+        const uint32_t sea_words = c.sea_bytes >> 2;
+        const uint32_t *sea32 = reinterpret_cast<const uint32_t *>(a.seav + sea);
+        uint32_t *stage32 = reinterpret_cast<uint32_t *>(sea8);
+        for (uint32_t w0 = 0; staged && w0 < sea_words; w0 += 64 * 8) {
             uint32_t v[8];
 #pragma unroll
             for (uint32_t k = 0; k < 8; ++k) {
-                const uint32_t b = b0 + k * 64 + lane;
-                v[k] = load_se<MODE>(a, sea + (b < c.sea_bytes ? b : c.sea_bytes - 1));
+                const uint32_t w = w0 + k * 64 + lane;
+                v[k] = w0 + k * 64 < sea_words ? sea32[w < sea_words ? w : sea_words - 1] : 0u;
             }
 #pragma unroll
             for (uint32_t k = 0; k < 8; ++k)
-                if (b0 + k * 64 + lane < c.sea_bytes) sea8[b0 + k * 64 + lane] = (uint8_t)v[k];
+                if (w0 + k * 64 + lane < sea_words) stage32[w0 + k * 64 + lane] = v[k];
         }
         wave_lds_sync();
         // Row loops run over kMaxRows with constant indices (guarded by the row count), so the
