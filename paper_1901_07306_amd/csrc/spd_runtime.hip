@@ -1140,6 +1140,10 @@ spd_status close_args(spd_ctx *ctx, const Slot &sl, const CloseBuf &cb, CloseArg
     const uint64_t resident = (uint64_t)ctx->n_cu * ctx->close_per_cu[b / 128];
     a->parts_log2 = 0;
     while (a->parts_log2 < 6 && ((uint64_t)a->n_rp << (a->parts_log2 + 1)) <= resident * waves) a->parts_log2++;
+    // In sliding mode a candidate's filter reads the counters behind its LDCs (8 or 16 bits a bit),
+    // so filtering, not the SEA, dominates a work item: every SEA is split at least in two, which
+    // halves the longest run of candidates one wavefront filters.
+    if (ctx->sliding && a->parts_log2 < 1) a->parts_log2 = 1;
     const uint64_t want = (((uint64_t)a->n_rp << a->parts_log2) + waves - 1) / waves;
     *grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, resident));
     return SPD_OK;
